@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the RQMC pricing path on one MI355X.
+
+Workload (default): the 80-forward, 3-factor LIBOR market model caplet book
+(quarterly forwards over 20 years, 4%->6% curve, humped vol, PCA-reduced
+exponential correlation, 80 ATM caplets + book), s = 240 Halton bases,
+N = 2^16 points x M = 1024 random-start replications, seed 3.  One step is
+one full pricing call: random starts, radical inverses, inverse normal,
+log-Euler paths, payoffs, theta_N^m, RQ_{M,N}, sd and SE -- inputs resident
+on the device, outputs left on the device.
+
+The headline form computes the paths in FP32 (digits, points, numeraire
+and reductions in FP64); the plain FP64 form is timed beside it on the same
+points, so both reach the same standard error.  The dominant kernel's
+launches are timed with HIP events recorded by the library on the launch
+stream; the CPU oracle is timed on a bounded sample of the same workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work per path of the 80-forward, 3-factor book (flops: FMA = 2,
+# add/mul = 1, each special function = 1): 3,240 forward-steps x 26, 240
+# inverse normals x 32, 80 payoffs x 12, 240 point divisions.
+FLOPS_PER_PATH_LMM80 = 93_040
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
+
+
+def _time_steps(fn, steps: int, warmup: int):
+    import torch
+    import paper_1408_5526_amd as rq
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    rq.timer_begin(steps)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    last = None
+    for _ in range(steps):
+        last = fn()
+    stop.record()
+    torch.cuda.synchronize()
+    kernel_ms, n = rq.timer_end()
+    total_ms = start.elapsed_time(stop)
+    return total_ms / steps, kernel_ms / max(n, 1), last
+
+
+def cpu_baseline(model, N: int, seed: int, m_per_core: int):
+    import oracle as O
+    cores = O.num_threads()
+    m_sub = m_per_core * cores
+    t0 = time.perf_counter()
+    O.price_caplets(model, N, m_sub, seed)
+    dt = time.perf_counter() - t0
+    return {"value": m_sub * N / dt, "unit": "paths/s", "cores": cores, "kind": "oracle",
+            "sample": f"{m_sub} of the 1024 replications at full N = {N} "
+                      f"({m_per_core} per thread), FP64, {dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--skip-fp64", action="store_true", help="do not time the FP64 comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-m-per-core", type=int, default=4)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(replications would shard across GPUs by m_offset)", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1408_5526_amd as rq
+    import rqmc_inputs as I
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    c = I.cfg3()
+    model, N, M, seed = c.model, c.N, c.M, c.seed
+
+    ws = torch.empty(max(rq.caplets_workspace(model, N, M, 0, "fp32"),
+                         rq.caplets_workspace(model, N, M, 0, "fp64")), dtype=torch.uint8, device=dev)
+
+    def step(prec):
+        return lambda: rq.price_caplets(model, N, M, seed, precision=prec, device=dev, ws=ws)
+
+    head = args.precision
+    ms, kms, res = _time_steps(step(head), args.steps, args.warmup)
+    se_head = res.se[-1].item()
+    rq_head = res.mean[-1].item()
+    out_extra = {}
+    if not args.skip_fp64 and head != "fp64":
+        ms64, kms64, res64 = _time_steps(step("fp64"), args.steps, args.warmup)
+        se64 = res64.se[-1].item()
+        out_extra = {
+            "fp64_paths_per_s": N * M / (ms64 / 1e3),
+            "fp64_ms_per_step": ms64,
+            "fp64_kernel_ms": kms64,
+            "speedup_vs_fp64": ms64 / ms,
+            "book_rq": {"fp32": rq_head, "fp64": res64.mean[-1].item()},
+            "book_se": {"fp32": se_head, "fp64": se64},
+            "se_ratio": se_head / se64,
+            "book_rel_diff_fp32_vs_fp64": abs(rq_head - res64.mean[-1].item()) / abs(res64.mean[-1].item()),
+        }
+
+    dtype = "f32" if head == "fp32" else "f64"
+    achieved = FLOPS_PER_PATH_LMM80 * N * M / (kms / 1e3) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    line = {
+        "metric": "RQMC paths/s + Greeks/s (LMM 80-fwd caplets) vs plain FP64, at equal std err",
+        "value": N * M / (ms / 1e3),
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": "lmm80_3f_caplet_book", "n_fwd": 80, "n_factors": 3, "s": 240,
+                   "N": N, "M": M, "seed": seed, "precision": head, "greeks": False},
+        "greeks_per_s": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "lmm_kernel<80,3,%s>" % ("float" if dtype == "f32" else "double"),
+                     "kernel_ms": kms},
+    }
+    line.update(out_extra)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(model, N, seed, args.cpu_m_per_core)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

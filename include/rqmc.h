@@ -1,0 +1,195 @@
+/*
+ * rqmc.h -- C ABI of the MI355X (gfx950) randomized quasi-Monte Carlo
+ * pricing library.
+ *
+ * Method (Xu & Okten, "High Performance Financial Simulation Using
+ * Randomized Quasi-Monte Carlo Methods"):
+ *   - M independent randomisations of an s-dimensional Halton sequence
+ *     (random-start, optionally randomly permuted: "Rasrap", section
+ *     "Randomized-quasi Monte Carlo sequences", eqs. (1)-(3), Algorithm 3);
+ *   - each point mapped through the inverse normal CDF;
+ *   - LIBOR market model caplets (SDE of the caplet section, log-Euler,
+ *     spot measure) or Caflisch mortgage-backed securities (MBS section);
+ *   - estimates theta_N^m = (1/N) sum_i f(q_i^m), the grand average
+ *     RQ_{M,N} = (1/M) sum_m theta_N^m, its sample standard deviation and
+ *     standard error (Introduction).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Points.  Replication m (global index m_offset + m) in dimension j uses
+ *   the j-th prime p_j (p_0 = 2), D_j = max{D : p_j^D <= 2^53} digits,
+ *   P_j = p_j^{D_j}, and a start n_j^m uniform on [0, P_j) drawn from
+ *   SplitMix64 (Steele, Lea & Flood 2014) keyed by (seed, m_global, j).
+ *   Point i (0-based) is x_{i,j}^m = phi_{p_j}((n_j^m + i) mod P_j), the
+ *   radical inverse with D_j digits, returned as the correctly rounded FP64
+ *   value of the exact rational R/P_j.  Point 0 of a replication is
+ *   phi(n), as in Algorithm 3, step 2.
+ * Flags (bitwise or):
+ *   RQ_START_ZERO   every start is 0: plain Halton (one replication
+ *                   suffices; the others repeat it).
+ *   RQ_PERM_RANDOM  one random digit permutation per base (eq. (3)),
+ *                   shared by all replications; digits above the top
+ *                   nonzero digit stay unpermuted.
+ *   RQ_OUT_DIGITS   rq_sequence only: emit the exact integers R (uint64)
+ *                   instead of the FP64 points.
+ * Normals.  Dimension j of a path maps to z = Phi^{-1}(x) (Wichura's
+ *   AS241 in FP64; the FP32 form folds r = min(x, 1-x) in FP64 first).
+ * Memory.  Every pointer named "device" is a device (HBM) address on the
+ *   current HIP device; every pointer named "host" is host memory read
+ *   during the call only.  The caller owns all buffers, including the
+ *   workspace `ws` (device, 256-byte aligned, at least the size returned
+ *   by the matching *_workspace function).  The library keeps no device
+ *   state between calls: concurrent calls need distinct workspaces.
+ * Streams.  `stream` is a hipStream_t (NULL = the legacy default stream).
+ *   Work is enqueued asynchronously; results are valid once the stream
+ *   has been synchronised.  The small per-call parameter tables are copied
+ *   from host memory with hipMemcpyAsync, which HIP may perform
+ *   synchronously for pageable memory.
+ * Errors.  Arguments are validated before anything is enqueued; a non-OK
+ *   status means nothing was launched unless it is RQ_EHIP.  The message of
+ *   the last non-OK status of the calling thread is rq_last_error().  The
+ *   library never aborts or exits.
+ */
+#ifndef RQMC_H
+#define RQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RQ_OK = 0,
+    RQ_EINVAL = 1,        /* null pointer, non-positive size, bad model value */
+    RQ_ERANGE = 2,        /* size beyond what the method or library supports */
+    RQ_ENOMEM = 3,        /* host allocation failed */
+    RQ_EHIP = 4,          /* a HIP call failed; see rq_last_error() */
+    RQ_EWORKSPACE = 5,    /* ws_bytes smaller than required, or ws misaligned */
+    RQ_EUNSUPPORTED = 6   /* valid request outside this build's capabilities */
+} rq_status;
+
+typedef enum { RQ_FP64 = 0, RQ_FP32 = 1 } rq_precision;
+
+enum {
+    RQ_START_RANDOM = 0,
+    RQ_START_ZERO = 1,
+    RQ_PERM_RANDOM = 2,
+    RQ_OUT_DIGITS = 4
+};
+
+/* Limits of this build. */
+#define RQ_MAX_DIM 4096          /* s <= 4096 (primes up to 38873)          */
+#define RQ_MAX_FWD 80            /* LIBOR forwards per model                */
+#define RQ_MAX_FACTORS 3         /* factors d of the LIBOR model            */
+#define RQ_MAX_MONTHS 4096       /* MBS term in months                      */
+#define RQ_MAX_REPLICATION (1LL << 40)  /* m_offset + M                    */
+
+/* LIBOR market model (caplet section).  Forwards L_1..L_n over
+ * [T_n, T_n + delta] with T_n = n*delta; the simulation steps from one
+ * tenor date to the next (step delta) under the spot measure with the
+ * log-Euler form of the discretised SDE.  Constant vol vectors
+ * a_n = sigma[n] * loadings[n-1][:].  Path dimension k*n_factors + f drives
+ * factor f of step k (s = n_fwd * n_factors).
+ *   L0        host [n_fwd+1]  L_0(0)..L_n(0) > 0; L_0(0) only enters the
+ *                             numeraire (1 + delta L_0(0)).
+ *   sigma     host [n_fwd+1]  sigma[n] >= 0 for n >= 1; sigma[0] unused.
+ *   loadings  host [n_fwd][n_factors], row-major, each row of unit length
+ *                             (|row| - 1| <= 1e-9).
+ *   strike    host [n_fwd]    K_1..K_n; NaN = no caplet on that forward.
+ * Outputs per path (n_out = n_fwd + 1): o = n-1 is the caplet on L_n,
+ * delta (L_n(T_n) - K_n)^+ paid at T_{n+1}, divided by the spot numeraire
+ * prod_{j=0..n} (1 + delta L_j(T_j)); o = n_fwd is the book (sum). */
+typedef struct {
+    int n_fwd;
+    int n_factors;
+    double delta;
+    const double *L0;
+    const double *sigma;
+    const double *loadings;
+    const double *strike;
+} rq_lmm_model;
+
+/* Caflisch MBS model (MBS section), unit principal, level payment
+ * c = i0/(1-(1+i0)^{-months}); monthly rate i_k = K0 e^{sigma z_k} i_{k-1}
+ * with K0 = exp(-sigma^2/2); prepayment w_k = K1 + K2 atan(K3 i_k + K4);
+ * PV = sum_k u_k c r_k ((1-w_k) + w_k c_k).  One output per path (n_out =
+ * 1); dimension k-1 drives month k (s = months). */
+typedef struct {
+    int months;
+    double i0, sigma, K1, K2, K3, K4;
+} rq_mbs_params;
+
+/* Results, all device pointers owned by the caller, FP64:
+ *   theta  [M][n_out]  per-replication estimates theta_N^m
+ *   mean   [n_out]     RQ_{M,N}
+ *   sd     [n_out]     sample standard deviation of theta (denominator
+ *                      M-1; NaN when M == 1)
+ *   se     [n_out]     sd / sqrt(M)
+ * Any of mean/sd/se may be NULL to skip it; theta is required. */
+typedef struct {
+    double *theta;
+    double *mean;
+    double *sd;
+    double *se;
+} rq_result;
+
+/* Workspace sizes in bytes for the call with the same arguments.
+ * Return 0 when the arguments would be rejected (rq_last_error says why). */
+size_t rq_sequence_workspace(int s, int64_t N, int M, int flags);
+size_t rq_caplets_workspace(const rq_lmm_model *model, int64_t N, int M, int flags,
+                            rq_precision prec);
+size_t rq_mbs_workspace(const rq_mbs_params *params, int64_t N, int M, int flags,
+                        rq_precision prec);
+
+/* sequence(s, N, M, seed): the points themselves (Algorithm 3 for every
+ * base, all replications in one launch).
+ *   out  device [M][N][s] FP64 points, or uint64 integers R when
+ *        RQ_OUT_DIGITS is set (x = R / P_j).
+ * Limits: s <= RQ_MAX_DIM, N <= P_j for every j, m_offset + M <=
+ * RQ_MAX_REPLICATION, M*N*s*8 bytes addressable. */
+rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t m_offset,
+                      void *out, void *ws, size_t ws_bytes, void *stream);
+
+/* price_caplets(model, N, M): caplets and book of the LIBOR market model.
+ *   out       results with n_out = n_fwd + 1
+ *   per_path  optional device [M][N][n_out] FP64: every path's discounted
+ *             payoffs (a verification hook; NULL in production)
+ *   prec      RQ_FP64: all path arithmetic in FP64.  RQ_FP32: forwards,
+ *             drifts and normals in FP32; digits, points, numeraire,
+ *             payoffs and all reductions stay FP64. */
+rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t seed,
+                           int64_t m_offset, int flags, rq_precision prec,
+                           const rq_result *out, double *per_path, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* price_mbs(params, N, M): present value of the mortgage pool.
+ *   prec  RQ_FP32 keeps the rate, prepayment and pool fraction in FP32 and
+ *         the discount factor, cash-flow products and reductions in FP64. */
+rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t seed,
+                       int64_t m_offset, int flags, rq_precision prec, const rq_result *out,
+                       double *per_path, void *ws, size_t ws_bytes, void *stream);
+
+/* Kernel timing instrumentation.  Between rq_timer_begin and rq_timer_end
+ * every entry point records a pair of HIP events on its stream around its
+ * main path kernel (the LIBOR or MBS pricing kernel, or the sequence
+ * kernel), for the first max_launches calls of the process; setup, copies
+ * and reductions are outside the pair.  rq_timer_end waits for the recorded
+ * events and returns the summed kernel time (ms) and the number of timed
+ * launches.  Process-wide; not meant for concurrent use from several
+ * threads. */
+rq_status rq_timer_begin(int max_launches);
+rq_status rq_timer_end(double *total_ms, int *n_launches);
+
+/* Thread-local message describing the last non-OK status ("" if none). */
+const char *rq_last_error(void);
+
+/* Library version string. */
+const char *rq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RQMC_H */

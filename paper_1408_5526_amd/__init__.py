@@ -1,0 +1,276 @@
+"""Randomized quasi-Monte Carlo pricing on MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``librqmc.so`` (declared in
+``include/rqmc.h``): argument marshalling only.  Every step of the path --
+random starts, radical inverses, inverse normal, LIBOR / MBS paths,
+payoffs, reductions -- runs in the library's HIP kernels.  PyTorch provides
+device memory and the stream.  There is no CPU fallback: if the library is
+missing or no GPU is present the calls raise.
+
+The method is the one of Xu & Okten, "High Performance Financial Simulation
+Using Randomized Quasi-Monte Carlo Methods": M independent random-start
+(optionally permuted) Halton replications (Algorithm 3), theta_N^m per
+replication, the grand average RQ_{M,N} and its spread (Introduction), for
+LIBOR market model caplets (caplet section) and Caflisch MBS (MBS section).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librqmc.so")
+
+RQ_OK, RQ_EINVAL, RQ_ERANGE, RQ_ENOMEM, RQ_EHIP, RQ_EWORKSPACE, RQ_EUNSUPPORTED = range(7)
+FP64, FP32 = 0, 1
+START_RANDOM, START_ZERO, PERM_RANDOM, OUT_DIGITS = 0, 1, 2, 4
+
+_dp = C.POINTER(C.c_double)
+
+
+class RqError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rq status {status}: {msg}")
+        self.status = status
+
+
+class rq_lmm_model(C.Structure):
+    _fields_ = [("n_fwd", C.c_int), ("n_factors", C.c_int), ("delta", C.c_double),
+                ("L0", _dp), ("sigma", _dp), ("loadings", _dp), ("strike", _dp)]
+
+
+class rq_mbs_params(C.Structure):
+    _fields_ = [("months", C.c_int), ("i0", C.c_double), ("sigma", C.c_double),
+                ("K1", C.c_double), ("K2", C.c_double), ("K3", C.c_double), ("K4", C.c_double)]
+
+
+class rq_result(C.Structure):
+    _fields_ = [("theta", C.c_void_p), ("mean", C.c_void_p), ("sd", C.c_void_p),
+                ("se", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(LIB_PATH)
+    L.rq_last_error.restype = C.c_char_p
+    L.rq_last_error.argtypes = []
+    L.rq_version.restype = C.c_char_p
+    L.rq_version.argtypes = []
+    L.rq_sequence_workspace.restype = C.c_size_t
+    L.rq_sequence_workspace.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int]
+    L.rq_caplets_workspace.restype = C.c_size_t
+    L.rq_caplets_workspace.argtypes = [C.POINTER(rq_lmm_model), C.c_int64, C.c_int, C.c_int, C.c_int]
+    L.rq_mbs_workspace.restype = C.c_size_t
+    L.rq_mbs_workspace.argtypes = [C.POINTER(rq_mbs_params), C.c_int64, C.c_int, C.c_int, C.c_int]
+    L.rq_sequence.restype = C.c_int
+    L.rq_sequence.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_uint64, C.c_int, C.c_int64,
+                              C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.rq_price_caplets.restype = C.c_int
+    L.rq_price_caplets.argtypes = [C.POINTER(rq_lmm_model), C.c_int64, C.c_int, C.c_uint64, C.c_int64,
+                                   C.c_int, C.c_int, C.POINTER(rq_result), C.c_void_p, C.c_void_p,
+                                   C.c_size_t, C.c_void_p]
+    L.rq_price_mbs.restype = C.c_int
+    L.rq_price_mbs.argtypes = [C.POINTER(rq_mbs_params), C.c_int64, C.c_int, C.c_uint64, C.c_int64,
+                               C.c_int, C.c_int, C.POINTER(rq_result), C.c_void_p, C.c_void_p,
+                               C.c_size_t, C.c_void_p]
+    L.rq_timer_begin.restype = C.c_int
+    L.rq_timer_begin.argtypes = [C.c_int]
+    L.rq_timer_end.restype = C.c_int
+    L.rq_timer_end.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().rq_last_error().decode()
+
+
+def _check(st: int):
+    if st != RQ_OK:
+        raise RqError(st, last_error())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _device(device):
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the RQMC library runs on MI355X only")
+    return torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+
+
+def _stream(device):
+    return C.c_void_p(_torch().cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+# model marshalling (host arrays stay alive for the duration of the call)
+# ---------------------------------------------------------------------------
+class _LmmHost:
+    def __init__(self, model):
+        self.L0 = np.ascontiguousarray(model.L0, dtype=np.float64)
+        self.sigma = np.ascontiguousarray(model.sigma, dtype=np.float64)
+        self.b = np.ascontiguousarray(model.loadings, dtype=np.float64).reshape(-1)
+        self.K = np.ascontiguousarray(model.strike, dtype=np.float64)
+        self.c = rq_lmm_model(int(model.n_fwd), int(model.n_factors), float(model.delta),
+                              self.L0.ctypes.data_as(_dp), self.sigma.ctypes.data_as(_dp),
+                              self.b.ctypes.data_as(_dp), self.K.ctypes.data_as(_dp))
+
+
+def _mbs_c(p) -> rq_mbs_params:
+    return rq_mbs_params(int(p.months), float(p.i0), float(p.sigma), float(p.K1), float(p.K2),
+                         float(p.K3), float(p.K4))
+
+
+@dataclass
+class Result:
+    """Per-replication estimates theta [M][n_out], RQ, sd (M-1), SE, all FP64
+    device tensors; per_path [M][N][n_out] when requested."""
+    theta: object
+    mean: object
+    sd: object
+    se: object
+    per_path: Optional[object] = None
+
+
+def _result(M: int, n_out: int, device):
+    torch = _torch()
+    theta = torch.empty((M, n_out), dtype=torch.float64, device=device)
+    mean = torch.empty(n_out, dtype=torch.float64, device=device)
+    sd = torch.empty(n_out, dtype=torch.float64, device=device)
+    se = torch.empty(n_out, dtype=torch.float64, device=device)
+    c = rq_result(theta.data_ptr(), mean.data_ptr(), sd.data_ptr(), se.data_ptr())
+    return Result(theta, mean, sd, se), c
+
+
+def _prec(precision) -> int:
+    if precision in (FP64, "fp64", "f64", "float64"):
+        return FP64
+    if precision in (FP32, "fp32", "f32", "float32"):
+        return FP32
+    raise ValueError(f"unknown precision {precision!r}")
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+def sequence_workspace(s: int, N: int, M: int, flags: int = 0) -> int:
+    n = lib().rq_sequence_workspace(s, N, M, flags)
+    if n == 0:
+        raise RqError(RQ_EINVAL, last_error())
+    return n
+
+
+def sequence(s: int, N: int, M: int, seed: int, flags: int = 0, m_offset: int = 0,
+             device=None, out=None, ws=None):
+    """Points of M random-start Halton replications: tensor [M][N][s], FP64
+    (or uint64 integers R = x * P_j with flags | OUT_DIGITS)."""
+    torch = _torch()
+    dev = _device(device)
+    dtype = torch.int64 if flags & OUT_DIGITS else torch.float64
+    if out is None:
+        out = torch.empty((M, N, s), dtype=dtype, device=dev)
+    need = sequence_workspace(s, N, M, flags)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    _check(lib().rq_sequence(s, N, M, seed, flags, m_offset, C.c_void_p(out.data_ptr()),
+                             C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)))
+    return out
+
+
+def caplets_workspace(model, N: int, M: int, flags: int = 0, precision="fp64") -> int:
+    h = _LmmHost(model)
+    n = lib().rq_caplets_workspace(C.byref(h.c), N, M, flags, _prec(precision))
+    if n == 0:
+        raise RqError(RQ_EINVAL, last_error())
+    return n
+
+
+def price_caplets(model, N: int, M: int, seed: int, m_offset: int = 0, flags: int = 0,
+                  precision="fp64", per_path: bool = False, device=None, ws=None) -> Result:
+    """Caplets on every forward with a strike, plus the book (last output),
+    n_out = n_fwd + 1."""
+    torch = _torch()
+    dev = _device(device)
+    h = _LmmHost(model)
+    prec = _prec(precision)
+    n_out = model.n_fwd + 1
+    res, c = _result(M, n_out, dev)
+    pp = torch.empty((M, N, n_out), dtype=torch.float64, device=dev) if per_path else None
+    need = lib().rq_caplets_workspace(C.byref(h.c), N, M, flags, prec)
+    if need == 0:
+        raise RqError(RQ_EINVAL, last_error())
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    _check(lib().rq_price_caplets(C.byref(h.c), N, M, seed, m_offset, flags, prec, C.byref(c),
+                                  C.c_void_p(pp.data_ptr() if pp is not None else 0),
+                                  C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)))
+    res.per_path = pp
+    return res
+
+
+def mbs_workspace(params, N: int, M: int, flags: int = 0, precision="fp64") -> int:
+    p = _mbs_c(params)
+    n = lib().rq_mbs_workspace(C.byref(p), N, M, flags, _prec(precision))
+    if n == 0:
+        raise RqError(RQ_EINVAL, last_error())
+    return n
+
+
+def price_mbs(params, N: int, M: int, seed: int, m_offset: int = 0, flags: int = 0,
+              precision="fp64", per_path: bool = False, device=None, ws=None) -> Result:
+    """Present value of the MBS pool, n_out = 1."""
+    torch = _torch()
+    dev = _device(device)
+    p = _mbs_c(params)
+    prec = _prec(precision)
+    res, c = _result(M, 1, dev)
+    pp = torch.empty((M, N, 1), dtype=torch.float64, device=dev) if per_path else None
+    need = lib().rq_mbs_workspace(C.byref(p), N, M, flags, prec)
+    if need == 0:
+        raise RqError(RQ_EINVAL, last_error())
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    _check(lib().rq_price_mbs(C.byref(p), N, M, seed, m_offset, flags, prec, C.byref(c),
+                              C.c_void_p(pp.data_ptr() if pp is not None else 0),
+                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)))
+    res.per_path = pp
+    return res
+
+
+def timer_begin(max_launches: int = 1000) -> None:
+    """Start recording HIP events around every main path kernel launch."""
+    _check(lib().rq_timer_begin(max_launches))
+
+
+def timer_end():
+    """(total kernel ms, number of timed launches) since timer_begin."""
+    ms = C.c_double(0.0)
+    n = C.c_int(0)
+    _check(lib().rq_timer_end(C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def version() -> str:
+    return lib().rq_version().decode()

@@ -1,0 +1,614 @@
+// rq_abi.cpp -- the C ABI: argument validation, per-dimension tables,
+// workspace layout and the launch sequence of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/rqmc.h"
+#include "rq_internal.h"
+
+namespace {
+
+using rq::BaseEnt;
+using rq::StartEnt;
+
+thread_local std::string g_err;
+
+rq_status fail(rq_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define RQ_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(RQ_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+// Optional kernel timer (rq_timer_begin / rq_timer_end).
+struct KernelTimer {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // pairs
+    size_t used = 0;
+} g_timer;
+
+struct TimedRegion {
+    hipStream_t st;
+    hipEvent_t stop = nullptr;
+    explicit TimedRegion(hipStream_t s) : st(s)
+    {
+        std::lock_guard<std::mutex> lk(g_timer.mu);
+        if (g_timer.on && 2 * (g_timer.used + 1) <= g_timer.ev.size()) {
+            hipEventRecord(g_timer.ev[2 * g_timer.used], st);
+            stop = g_timer.ev[2 * g_timer.used + 1];
+            ++g_timer.used;
+        }
+    }
+    ~TimedRegion()
+    {
+        if (stop) hipEventRecord(stop, st);
+    }
+};
+
+// The first RQ_MAX_DIM primes (sieve of Eratosthenes).
+const std::vector<uint32_t> &primes()
+{
+    static const std::vector<uint32_t> tab = [] {
+        std::vector<uint32_t> out;
+        const uint32_t lim = 40000;
+        std::vector<char> comp(lim + 1, 0);
+        for (uint32_t q = 2; q <= lim && (int)out.size() < RQ_MAX_DIM; ++q) {
+            if (comp[q]) continue;
+            out.push_back(q);
+            for (uint64_t r = (uint64_t)q * q; r <= lim; r += q) comp[r] = 1;
+        }
+        return out;
+    }();
+    return tab;
+}
+
+constexpr uint64_t kTwo53 = 1ull << 53;
+constexpr uint64_t kLowLimit = 1ull << 30;   // p^L must stay below 2^30 (v < 2^31)
+
+uint64_t ipow(uint64_t p, uint32_t e)
+{
+    uint64_t r = 1;
+    while (e--) r *= p;
+    return r;
+}
+
+uint32_t digits_D(uint64_t p)
+{
+    uint32_t D = 0;
+    uint64_t P = 1;
+    while (P <= kTwo53 / p) { P *= p; ++D; }
+    return D;
+}
+
+uint32_t low_digits(uint64_t p, int64_t S)
+{
+    uint32_t L = 1;
+    uint64_t v = p;
+    while ((int64_t)v < S) { v *= p; ++L; }
+    return L;
+}
+
+// Geometry of the index range: segment length S (power of two, >= 256 so a
+// block never straddles two segments) such that p_j^{L_j} < 2^30 for every
+// dimension; S never exceeds the next power of two of N.
+struct Geometry {
+    int64_t S = 0;
+    int log2S = 0;
+    int n_seg = 0;
+};
+
+bool choose_geometry(int s, int64_t N, Geometry &g)
+{
+    const auto &pr = primes();
+    int64_t S = 256;
+    int lg = 8;
+    while (S < N && S < (int64_t)kLowLimit) { S <<= 1; ++lg; }
+    auto ok = [&](int64_t SS) {
+        for (int j = 0; j < s; ++j) {
+            uint64_t p = pr[j];
+            if (ipow(p, low_digits(p, SS)) >= kLowLimit) return false;
+        }
+        return true;
+    };
+    while (S > 256 && !ok(S)) { S >>= 1; --lg; }
+    if (!ok(S)) return false;
+    g.S = S;
+    g.log2S = lg;
+    g.n_seg = (int)((N + S - 1) / S);
+    return true;
+}
+
+// 1/p rounded toward +infinity.
+double inv_up(uint64_t p)
+{
+    double r = 1.0 / (double)p;
+    if (std::fma(r, (double)p, -1.0) < 0.0) r = std::nextafter(r, INFINITY);
+    return r;
+}
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014), random access by counter.
+uint64_t sm64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1ull) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Uniform on [0, range) by rejection from counters ctr0, ctr0+1, ...
+bool uniform_below(uint64_t seed, uint64_t ctr0, uint64_t range, uint64_t &out)
+{
+    const uint64_t rem = (0ull - range) % range;
+    for (uint64_t a = 0; a < 64; ++a) {
+        const uint64_t u = sm64_at(seed, ctr0 + a);
+        if (rem == 0 || u < 0ull - rem) { out = u % range; return true; }
+    }
+    return false;
+}
+
+// Host tables of the point geometry: BaseEnt[s] followed (when permuted)
+// by the packed u16 permutations.  Fisher-Yates per base from the
+// identity: step t = p-1..1 swaps sigma[t] and sigma[r], r uniform on
+// [0, t] with counters 2^60 + (j*4096 + t)*64 + attempt.
+struct PointTables {
+    std::vector<BaseEnt> base;
+    std::vector<uint16_t> perm;
+};
+
+rq_status build_point_tables(int s, const Geometry &g, uint64_t seed, int flags, PointTables &t)
+{
+    const auto &pr = primes();
+    t.base.resize(s);
+    uint32_t off = 0;
+    for (int j = 0; j < s; ++j) {
+        const uint64_t p = pr[j];
+        BaseEnt &b = t.base[j];
+        std::memset(&b, 0, sizeof b);
+        b.p = (uint32_t)p;
+        b.D = digits_D(p);
+        b.L = low_digits(p, g.S);
+        b.pL = (uint32_t)ipow(p, b.L);
+        b.P = ipow(p, b.D);
+        b.pDL = ipow(p, b.D - b.L);
+        b.pd = (double)p;
+        b.invp_up = inv_up(p);
+        b.pDLd = (double)b.pDL;
+        b.Pd = (double)b.P;
+        b.perm_off = off;
+        if (flags & RQ_PERM_RANDOM) off += (uint32_t)p;
+    }
+    if (flags & RQ_PERM_RANDOM) {
+        t.perm.resize(off);
+        for (int j = 0; j < s; ++j) {
+            const uint32_t p = t.base[j].p;
+            uint16_t *sg = t.perm.data() + t.base[j].perm_off;
+            for (uint32_t a = 0; a < p; ++a) sg[a] = (uint16_t)a;
+            for (uint32_t st = p - 1; st >= 1; --st) {
+                uint64_t r;
+                const uint64_t ctr = (1ull << 60) + ((uint64_t)j * 4096ull + st) * 64ull;
+                if (!uniform_below(seed, ctr, (uint64_t)st + 1, r))
+                    return fail(RQ_ERANGE, "permutation draw exhausted its attempts");
+                std::swap(sg[st], sg[r]);
+            }
+        }
+    }
+    return RQ_OK;
+}
+
+// Workspace layout.  Region offsets are 256-byte aligned.
+struct Layout {
+    size_t base = 0, perm = 0, model = 0, starts = 0, partial = 0, total = 0;
+    size_t host_bytes = 0;   // bytes staged from the host (base | perm | model)
+};
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout(int s, const Geometry &g, int M, int flags, size_t model_bytes, size_t partial_bytes)
+{
+    Layout L;
+    const auto &pr = primes();
+    size_t perm_elems = 0;
+    if (flags & RQ_PERM_RANDOM)
+        for (int j = 0; j < s; ++j) perm_elems += pr[j];
+    L.base = 0;
+    L.perm = al(sizeof(BaseEnt) * (size_t)s);
+    L.model = L.perm + al(perm_elems * sizeof(uint16_t));
+    L.host_bytes = L.model + model_bytes;
+    L.starts = al(L.host_bytes);
+    L.partial = L.starts + al(sizeof(StartEnt) * (size_t)M * (size_t)g.n_seg * (size_t)s);
+    L.total = L.partial + al(partial_bytes);
+    return L;
+}
+
+rq_status check_common(int s, int64_t N, int M, int flags, int64_t m_offset, Geometry &g)
+{
+    if (s < 1) return fail(RQ_EINVAL, "s must be >= 1 (got %d)", s);
+    if (N < 1) return fail(RQ_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
+    if (M < 1) return fail(RQ_EINVAL, "M must be >= 1 (got %d)", M);
+    if (m_offset < 0) return fail(RQ_EINVAL, "m_offset must be >= 0");
+    if (flags & ~(RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS))
+        return fail(RQ_EINVAL, "unknown flag bits 0x%x", flags);
+    if (s > RQ_MAX_DIM) return fail(RQ_ERANGE, "s = %d beyond the %d supported bases", s, RQ_MAX_DIM);
+    if (m_offset + (int64_t)M > RQ_MAX_REPLICATION)
+        return fail(RQ_ERANGE, "m_offset + M beyond 2^40");
+    const auto &pr = primes();
+    for (int j = 0; j < s; ++j) {
+        const uint64_t P = ipow(pr[j], digits_D(pr[j]));
+        if ((uint64_t)N > P)
+            return fail(RQ_ERANGE, "N = %lld exceeds P_%d = %llu (base %u)", (long long)N, j,
+                        (unsigned long long)P, pr[j]);
+    }
+    if (!choose_geometry(s, N, g)) return fail(RQ_ERANGE, "no segment length fits s = %d", s);
+    return RQ_OK;
+}
+
+rq_status check_ws(void *ws, size_t ws_bytes, size_t need)
+{
+    if (!ws) return fail(RQ_EINVAL, "workspace pointer is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(RQ_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(RQ_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    return RQ_OK;
+}
+
+// Stage the host tables, then run the setup kernel.
+rq_status stage_and_setup(const PointTables &pt, const std::vector<uint8_t> &model, const Layout &L,
+                          const Geometry &g, int s, int M, uint64_t seed, int64_t m_offset,
+                          int flags, uint8_t *ws, hipStream_t st)
+{
+    std::vector<uint8_t> host(L.host_bytes, 0);
+    std::memcpy(host.data() + L.base, pt.base.data(), sizeof(BaseEnt) * pt.base.size());
+    if (!pt.perm.empty())
+        std::memcpy(host.data() + L.perm, pt.perm.data(), pt.perm.size() * sizeof(uint16_t));
+    if (!model.empty()) std::memcpy(host.data() + L.model, model.data(), model.size());
+    RQ_HIP(hipMemcpyAsync(ws, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    rq::SetupArgs a;
+    a.base_dev = reinterpret_cast<BaseEnt *>(ws + L.base);
+    a.starts = reinterpret_cast<StartEnt *>(ws + L.starts);
+    a.perm = (flags & RQ_PERM_RANDOM) ? reinterpret_cast<const uint16_t *>(ws + L.perm) : nullptr;
+    a.seed = seed;
+    a.m_offset = m_offset;
+    a.s = s;
+    a.M = M;
+    a.n_seg = g.n_seg;
+    a.S = g.S;
+    a.flags = flags;
+    RQ_HIP(rq::launch_setup(a, st));
+    return RQ_OK;
+}
+
+rq::SeqGeom seq_geom(const Layout &L, const Geometry &g, uint8_t *ws, int s, int M, int64_t N, int flags)
+{
+    rq::SeqGeom sg;
+    sg.base = reinterpret_cast<const BaseEnt *>(ws + L.base);
+    sg.starts = reinterpret_cast<const StartEnt *>(ws + L.starts);
+    sg.perm = (flags & RQ_PERM_RANDOM) ? reinterpret_cast<const uint16_t *>(ws + L.perm) : nullptr;
+    sg.s = s;
+    sg.M = M;
+    sg.n_seg = g.n_seg;
+    sg.perm_on = (flags & RQ_PERM_RANDOM) ? 1 : 0;
+    sg.N = N;
+    sg.S = g.S;
+    sg.log2S = g.log2S;
+    return sg;
+}
+
+// ---- LIBOR model -----------------------------------------------------------
+
+rq_status check_lmm(const rq_lmm_model *m)
+{
+    if (!m) return fail(RQ_EINVAL, "model is NULL");
+    if (!m->L0 || !m->sigma || !m->loadings || !m->strike)
+        return fail(RQ_EINVAL, "model arrays must not be NULL");
+    if (m->n_fwd < 1) return fail(RQ_EINVAL, "n_fwd must be >= 1");
+    if (m->n_factors < 1) return fail(RQ_EINVAL, "n_factors must be >= 1");
+    if (m->n_fwd > RQ_MAX_FWD) return fail(RQ_EUNSUPPORTED, "n_fwd = %d > %d", m->n_fwd, RQ_MAX_FWD);
+    if (m->n_factors > RQ_MAX_FACTORS)
+        return fail(RQ_EUNSUPPORTED, "n_factors = %d > %d", m->n_factors, RQ_MAX_FACTORS);
+    if (!(m->delta > 0.0) || !std::isfinite(m->delta)) return fail(RQ_EINVAL, "delta must be > 0");
+    for (int n = 0; n <= m->n_fwd; ++n)
+        if (!(m->L0[n] > 0.0) || !std::isfinite(m->L0[n]))
+            return fail(RQ_EINVAL, "L0[%d] = %g must be finite and > 0", n, m->L0[n]);
+    for (int n = 1; n <= m->n_fwd; ++n)
+        if (!(m->sigma[n] >= 0.0) || !std::isfinite(m->sigma[n]))
+            return fail(RQ_EINVAL, "sigma[%d] = %g must be finite and >= 0", n, m->sigma[n]);
+    for (int n = 0; n < m->n_fwd; ++n) {
+        double q = 0.0;
+        for (int f = 0; f < m->n_factors; ++f) {
+            const double b = m->loadings[(size_t)n * m->n_factors + f];
+            if (!std::isfinite(b)) return fail(RQ_EINVAL, "loadings[%d] not finite", n);
+            q += b * b;
+        }
+        if (std::fabs(std::sqrt(q) - 1.0) > 1e-9)
+            return fail(RQ_EINVAL, "loadings row %d has norm %.17g, must be 1", n, std::sqrt(q));
+        const double K = m->strike[n];
+        if (!std::isnan(K) && !std::isfinite(K)) return fail(RQ_EINVAL, "strike[%d] infinite", n);
+    }
+    return RQ_OK;
+}
+
+// fwd table [n][8] FP64 then the same in FP32.
+std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
+{
+    const int nf = m->n_fwd, d = m->n_factors;
+    std::vector<double> t((size_t)nf * rq::kFwdRow, 0.0);
+    for (int n = 1; n <= nf; ++n) {
+        double *r = &t[(size_t)(n - 1) * rq::kFwdRow];
+        double an2 = 0.0;
+        for (int f = 0; f < d; ++f) {
+            const double a = m->sigma[n] * m->loadings[(size_t)(n - 1) * d + f];
+            r[f] = a;
+            an2 += a * a;
+        }
+        r[3] = -0.5 * an2 * m->delta;
+        const double K = m->strike[n - 1];
+        r[4] = std::isnan(K) ? 0.0 : K;
+        r[5] = m->L0[n];
+        r[6] = std::isnan(K) ? 0.0 : 1.0;
+    }
+    std::vector<uint8_t> out(t.size() * sizeof(double) + t.size() * sizeof(float));
+    std::memcpy(out.data(), t.data(), t.size() * sizeof(double));
+    float *f32 = reinterpret_cast<float *>(out.data() + t.size() * sizeof(double));
+    for (size_t q = 0; q < t.size(); ++q) f32[q] = (float)t[q];
+    return out;
+}
+
+int lmm_blocks(int64_t N) { return (int)((N + rq::kBlock - 1) / rq::kBlock); }
+
+// ---- MBS model ---------------------------------------------------------------
+
+rq_status check_mbs(const rq_mbs_params *p)
+{
+    if (!p) return fail(RQ_EINVAL, "params is NULL");
+    if (p->months < 1) return fail(RQ_EINVAL, "months must be >= 1");
+    if (p->months > RQ_MAX_MONTHS) return fail(RQ_ERANGE, "months = %d > %d", p->months, RQ_MAX_MONTHS);
+    if (!(p->i0 > 0.0) || !std::isfinite(p->i0)) return fail(RQ_EINVAL, "i0 must be > 0");
+    if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return fail(RQ_EINVAL, "sigma must be >= 0");
+    if (!std::isfinite(p->K1) || !std::isfinite(p->K2) || !std::isfinite(p->K3) || !std::isfinite(p->K4))
+        return fail(RQ_EINVAL, "K1..K4 must be finite");
+    return RQ_OK;
+}
+
+// c_k = sum_{j=0}^{K-k} (1+i0)^{-j} for k = 0..K (geometric series).
+std::vector<uint8_t> mbs_table(const rq_mbs_params *p)
+{
+    const int K = p->months;
+    std::vector<double> ck(K + 1, 0.0);
+    const double v = 1.0 / (1.0 + p->i0);
+    // accumulate from the end: c_K = 1, c_k = 1 + v c_{k+1}
+    ck[K] = 1.0;
+    for (int k = K - 1; k >= 1; --k) ck[k] = 1.0 + v * ck[k + 1];
+    std::vector<uint8_t> out(ck.size() * sizeof(double));
+    std::memcpy(out.data(), ck.data(), out.size());
+    return out;
+}
+
+rq_status finish(const rq_result *out, double *partial, int M, int n_blk, int n_out, int64_t N,
+                 hipStream_t st)
+{
+    rq::ReduceArgs r;
+    r.partial = partial;
+    r.theta = out->theta;
+    r.M = M;
+    r.n_blk = n_blk;
+    r.n_out = n_out;
+    r.Nd = (double)N;
+    RQ_HIP(rq::launch_reduce(r, st));
+    if (out->mean || out->sd || out->se) {
+        rq::FinalizeArgs f;
+        f.theta = out->theta;
+        f.mean = out->mean;
+        f.sd = out->sd;
+        f.se = out->se;
+        f.M = M;
+        f.n_out = n_out;
+        RQ_HIP(rq::launch_finalize(f, st));
+    }
+    return RQ_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+const char *rq_last_error(void) { return g_err.c_str(); }
+
+const char *rq_version(void) { return "rqmc-mi355x 0.1 (gfx950)"; }
+
+rq_status rq_timer_begin(int max_launches)
+{
+    if (max_launches < 1 || max_launches > 100000) return fail(RQ_EINVAL, "max_launches out of range");
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    if (g_timer.on) return fail(RQ_EINVAL, "timer already running");
+    g_timer.ev.assign(2 * (size_t)max_launches, nullptr);
+    for (auto &e : g_timer.ev) {
+        hipError_t h = hipEventCreate(&e);
+        if (h != hipSuccess) {
+            for (auto &x : g_timer.ev) if (x) hipEventDestroy(x);
+            g_timer.ev.clear();
+            return fail(RQ_EHIP, "hipEventCreate failed: %s", hipGetErrorString(h));
+        }
+    }
+    g_timer.used = 0;
+    g_timer.on = true;
+    return RQ_OK;
+}
+
+rq_status rq_timer_end(double *total_ms, int *n_launches)
+{
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    if (!g_timer.on) return fail(RQ_EINVAL, "timer not running");
+    g_timer.on = false;
+    double tot = 0.0;
+    rq_status st = RQ_OK;
+    for (size_t q = 0; q < g_timer.used; ++q) {
+        float ms = 0.0f;
+        hipError_t h = hipEventSynchronize(g_timer.ev[2 * q + 1]);
+        if (h == hipSuccess) h = hipEventElapsedTime(&ms, g_timer.ev[2 * q], g_timer.ev[2 * q + 1]);
+        if (h != hipSuccess && st == RQ_OK) st = fail(RQ_EHIP, "event timing failed: %s", hipGetErrorString(h));
+        tot += ms;
+    }
+    for (auto &e : g_timer.ev) hipEventDestroy(e);
+    g_timer.ev.clear();
+    if (total_ms) *total_ms = tot;
+    if (n_launches) *n_launches = (int)g_timer.used;
+    return st;
+}
+
+size_t rq_sequence_workspace(int s, int64_t N, int M, int flags)
+{
+    Geometry g;
+    if (check_common(s, N, M, flags, 0, g) != RQ_OK) return 0;
+    return layout(s, g, M, flags, 0, 0).total;
+}
+
+rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t m_offset, void *out,
+                      void *ws, size_t ws_bytes, void *stream)
+{
+    Geometry g;
+    rq_status stt = check_common(s, N, M, flags, m_offset, g);
+    if (stt) return stt;
+    if (!out) return fail(RQ_EINVAL, "out is NULL");
+    const Layout L = layout(s, g, M, flags, 0, 0);
+    if ((stt = check_ws(ws, ws_bytes, L.total))) return stt;
+    PointTables pt;
+    if ((stt = build_point_tables(s, g, seed, flags, pt))) return stt;
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t *w = (uint8_t *)ws;
+    if ((stt = stage_and_setup(pt, {}, L, g, s, M, seed, m_offset, flags, w, st))) return stt;
+    {
+        TimedRegion tr(st);
+        RQ_HIP(rq::launch_sequence(seq_geom(L, g, w, s, M, N, flags), flags, out, st));
+    }
+    return RQ_OK;
+}
+
+size_t rq_caplets_workspace(const rq_lmm_model *model, int64_t N, int M, int flags, rq_precision prec)
+{
+    if (check_lmm(model) != RQ_OK) return 0;
+    Geometry g;
+    const int s = model->n_fwd * model->n_factors;
+    if (check_common(s, N, M, flags, 0, g) != RQ_OK) return 0;
+    (void)prec;
+    const size_t mb = (size_t)model->n_fwd * rq::kFwdRow * (sizeof(double) + sizeof(float));
+    const size_t pb = (size_t)M * lmm_blocks(N) * (model->n_fwd + 1) * sizeof(double);
+    return layout(s, g, M, flags, mb, pb).total;
+}
+
+rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t seed, int64_t m_offset,
+                           int flags, rq_precision prec, const rq_result *out, double *per_path,
+                           void *ws, size_t ws_bytes, void *stream)
+{
+    rq_status stt = check_lmm(model);
+    if (stt) return stt;
+    if (flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "RQ_OUT_DIGITS applies to rq_sequence only");
+    if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
+    if (!out || !out->theta) return fail(RQ_EINVAL, "out->theta is NULL");
+    const int s = model->n_fwd * model->n_factors;
+    Geometry g;
+    if ((stt = check_common(s, N, M, flags, m_offset, g))) return stt;
+    const int n_blk = lmm_blocks(N);
+    const int n_out = model->n_fwd + 1;
+    if ((int64_t)n_blk * M >= (1ll << 31)) return fail(RQ_ERANGE, "N*M too large for one launch");
+    std::vector<uint8_t> tab = lmm_table(model);
+    const Layout L = layout(s, g, M, flags, tab.size(), (size_t)M * n_blk * n_out * sizeof(double));
+    if ((stt = check_ws(ws, ws_bytes, L.total))) return stt;
+    PointTables pt;
+    if ((stt = build_point_tables(s, g, seed, flags, pt))) return stt;
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t *w = (uint8_t *)ws;
+    if ((stt = stage_and_setup(pt, tab, L, g, s, M, seed, m_offset, flags, w, st))) return stt;
+    rq::LmmArgs a;
+    a.g = seq_geom(L, g, w, s, M, N, flags);
+    a.fwd = reinterpret_cast<const double *>(w + L.model);
+    a.partial = reinterpret_cast<double *>(w + L.partial);
+    a.per_path = per_path;
+    a.n_fwd = model->n_fwd;
+    a.n_out = n_out;
+    a.n_blk = n_blk;
+    a.delta = model->delta;
+    a.sqrt_delta = std::sqrt(model->delta);
+    a.num0 = 1.0 + model->delta * model->L0[0];
+    {
+        TimedRegion tr(st);
+        RQ_HIP(rq::launch_lmm(a, model->n_factors, prec == RQ_FP32, st));
+    }
+    return finish(out, a.partial, M, n_blk, n_out, N, st);
+}
+
+size_t rq_mbs_workspace(const rq_mbs_params *params, int64_t N, int M, int flags, rq_precision prec)
+{
+    if (check_mbs(params) != RQ_OK) return 0;
+    Geometry g;
+    if (check_common(params->months, N, M, flags, 0, g) != RQ_OK) return 0;
+    (void)prec;
+    const size_t mb = (size_t)(params->months + 1) * sizeof(double);
+    const size_t pb = (size_t)M * lmm_blocks(N) * sizeof(double);
+    return layout(params->months, g, M, flags, mb, pb).total;
+}
+
+rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t seed, int64_t m_offset,
+                       int flags, rq_precision prec, const rq_result *out, double *per_path, void *ws,
+                       size_t ws_bytes, void *stream)
+{
+    rq_status stt = check_mbs(params);
+    if (stt) return stt;
+    if (flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "RQ_OUT_DIGITS applies to rq_sequence only");
+    if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
+    if (!out || !out->theta) return fail(RQ_EINVAL, "out->theta is NULL");
+    const int s = params->months;
+    Geometry g;
+    if ((stt = check_common(s, N, M, flags, m_offset, g))) return stt;
+    const int n_blk = lmm_blocks(N);
+    if ((int64_t)n_blk * M >= (1ll << 31)) return fail(RQ_ERANGE, "N*M too large for one launch");
+    std::vector<uint8_t> tab = mbs_table(params);
+    const Layout L = layout(s, g, M, flags, tab.size(), (size_t)M * n_blk * sizeof(double));
+    if ((stt = check_ws(ws, ws_bytes, L.total))) return stt;
+    PointTables pt;
+    if ((stt = build_point_tables(s, g, seed, flags, pt))) return stt;
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t *w = (uint8_t *)ws;
+    if ((stt = stage_and_setup(pt, tab, L, g, s, M, seed, m_offset, flags, w, st))) return stt;
+    rq::MbsArgs a;
+    a.g = seq_geom(L, g, w, s, M, N, flags);
+    a.ck = reinterpret_cast<const double *>(w + L.model);
+    a.partial = reinterpret_cast<double *>(w + L.partial);
+    a.per_path = per_path;
+    a.months = params->months;
+    a.n_blk = n_blk;
+    a.i0 = params->i0;
+    a.sig = params->sigma;
+    a.K0 = std::exp(-0.5 * params->sigma * params->sigma);
+    a.K1 = params->K1;
+    a.K2 = params->K2;
+    a.K3 = params->K3;
+    a.K4 = params->K4;
+    a.c = params->i0 / (1.0 - std::pow(1.0 + params->i0, -(double)params->months));
+    {
+        TimedRegion tr(st);
+        RQ_HIP(rq::launch_mbs(a, prec == RQ_FP32, st));
+    }
+    return finish(out, a.partial, M, n_blk, 1, N, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// rq_device.h -- device building blocks shared by the pricing kernels:
+// the in-register radical inverse, the inverse normal CDF, deterministic
+// wave reductions and compensated accumulation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rq_internal.h"
+
+namespace rq {
+
+// ---------------------------------------------------------------------------
+// Radical inverse (eqs. (1)-(3)) of the index (n + i) mod P for one lane.
+//
+// The segment table holds the split of the replication's start; the lane
+// expands only the L low base-p digits of v = nlo + t.  Digit extraction is
+// exact FP64 arithmetic: for integers 0 <= v < 2^31 and p < 2^20,
+// trunc(RN(v * RU(1/p))) == floor(v/p) (the rounded product never reaches
+// the next integer because (p-1)/p + 2^-21 < 1 - 2^-23), the remainder
+// fma(-q, p, v) is exact, and the Horner accumulation R = R*p + a stays an
+// exact integer below 2^53.  The returned R is P * phi exactly; the point
+// is RN(R / P), one IEEE division.
+//
+// With a digit permutation sigma (eq. (3)) digits above the top nonzero
+// digit of the whole index stay 0: when the high part (hi + c) is zero
+// (bit c of hz) the zero digits of v above its own top digit are leading
+// zeros too; they are exactly the digits met once the remaining value is 0.
+// ---------------------------------------------------------------------------
+struct PointCtx {
+    double pd, invp, pDLd, Pd;
+    uint32_t L, pL, perm_off;
+};
+
+__device__ __forceinline__ PointCtx load_base(const BaseEnt *__restrict__ base, int j)
+{
+    PointCtx c;
+    const BaseEnt *b = base + j;
+    c.pd = b->pd;
+    c.invp = b->invp_up;
+    c.pDLd = b->pDLd;
+    c.Pd = b->Pd;
+    c.L = b->L;
+    c.pL = b->pL;
+    c.perm_off = b->perm_off;
+    return c;
+}
+
+// R of the lane's point as an exact FP64 integer.
+template <bool PERM>
+__device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt *__restrict__ e,
+                                           uint32_t t, const uint16_t *__restrict__ perm)
+{
+    uint32_t vi = e->nlo + t;                 // < 2 p^L <= 2^31
+    const bool carry = vi >= c.pL;
+    vi -= carry ? c.pL : 0u;
+    const double rhi = carry ? e->rhi1 : e->rhi0;
+    double v = (double)vi;
+    double R = 0.0;
+    if (!PERM) {
+        for (uint32_t q = 0; q < c.L; ++q) {
+            const double qt = __builtin_trunc(v * c.invp);
+            const double a = __builtin_fma(-qt, c.pd, v);
+            R = __builtin_fma(R, c.pd, a);
+            v = qt;
+        }
+    } else {
+        const bool hz = (e->hz >> (carry ? 1 : 0)) & 1u;
+        const uint16_t *sg = perm + c.perm_off;
+        for (uint32_t q = 0; q < c.L; ++q) {
+            const double qt = __builtin_trunc(v * c.invp);
+            const double a = __builtin_fma(-qt, c.pd, v);
+            const double dig = (hz && v == 0.0) ? 0.0 : (double)sg[(int)a];
+            R = __builtin_fma(R, c.pd, dig);
+            v = qt;
+        }
+    }
+    return __builtin_fma(R, c.pDLd, rhi);
+}
+
+template <bool PERM>
+__device__ __forceinline__ double radinv_x(const PointCtx &c, const StartEnt *__restrict__ e,
+                                           uint32_t t, const uint16_t *__restrict__ perm)
+{
+    return radinv_R<PERM>(c, e, t, perm) / c.Pd;
+}
+
+// ---------------------------------------------------------------------------
+// Inverse standard normal CDF: Wichura, "Algorithm AS 241" (Applied
+// Statistics 37, 1988), PPND16 rational approximations on three regions:
+// |u - 1/2| <= 0.425; r = sqrt(-ln min(u,1-u)) <= 5; r > 5.  The fold
+// min(u, 1-u) is formed in FP64 and clamped to 2^-64 (u = 0 occurs only for
+// the index whose digits are all zero).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T as241_central(T q)
+{
+    const T r = T(0.180625) - q * q;
+    T num = T(2.5090809287301226727e3);
+    num = num * r + T(3.3430575583588128105e4);
+    num = num * r + T(6.7265770927008700853e4);
+    num = num * r + T(4.5921953931549871457e4);
+    num = num * r + T(1.3731693765509461125e4);
+    num = num * r + T(1.9715909503065514427e3);
+    num = num * r + T(1.3314166789178437745e2);
+    num = num * r + T(3.3871328727963666080e0);
+    T den = T(5.2264952788528545610e3);
+    den = den * r + T(2.8729085735721942674e4);
+    den = den * r + T(3.9307895800092710610e4);
+    den = den * r + T(2.1213794301586595867e4);
+    den = den * r + T(5.3941960214247511077e3);
+    den = den * r + T(6.8718700749205790830e2);
+    den = den * r + T(4.2313330701600911252e1);
+    den = den * r + T(1.0);
+    return q * num / den;
+}
+
+template <typename T>
+__device__ __forceinline__ T as241_tail(T r)   // r = sqrt(-ln u_folded)
+{
+    if (r <= T(5.0)) {
+        r -= T(1.6);
+        T num = T(7.74545014278341407640e-4);
+        num = num * r + T(2.27238449892691845833e-2);
+        num = num * r + T(2.41780725177450611770e-1);
+        num = num * r + T(1.27045825245236838258e0);
+        num = num * r + T(3.64784832476320460504e0);
+        num = num * r + T(5.76949722146069140550e0);
+        num = num * r + T(4.63033784615654529590e0);
+        num = num * r + T(1.42343711074968357734e0);
+        T den = T(1.05075007164441684324e-9);
+        den = den * r + T(5.47593808499534494600e-4);
+        den = den * r + T(1.51986665636164571966e-2);
+        den = den * r + T(1.48103976427480074590e-1);
+        den = den * r + T(6.89767334985100004550e-1);
+        den = den * r + T(1.67638483018380384940e0);
+        den = den * r + T(2.05319162663775882187e0);
+        den = den * r + T(1.0);
+        return num / den;
+    }
+    r -= T(5.0);
+    T num = T(2.01033439929228813265e-7);
+    num = num * r + T(2.71155556874348757815e-5);
+    num = num * r + T(1.24266094738807843860e-3);
+    num = num * r + T(2.65321895265761230930e-2);
+    num = num * r + T(2.96560571828504891230e-1);
+    num = num * r + T(1.78482653991729133580e0);
+    num = num * r + T(5.46378491116411436990e0);
+    num = num * r + T(6.65790464350110377720e0);
+    T den = T(2.04426310338993978564e-15);
+    den = den * r + T(1.42151175831644588870e-7);
+    den = den * r + T(1.84631831751005468180e-5);
+    den = den * r + T(7.86869131145613259100e-4);
+    den = den * r + T(1.48753612908506148525e-2);
+    den = den * r + T(1.36929880922735805310e-1);
+    den = den * r + T(5.99832206555887937690e-1);
+    den = den * r + T(1.0);
+    return num / den;
+}
+
+__device__ __forceinline__ double inv_normal(double u, double)
+{
+    const double q = u - 0.5;
+    if (fabs(q) <= 0.425) return as241_central<double>(q);
+    double r = q < 0.0 ? u : 1.0 - u;
+    r = fmax(r, 0x1p-64);
+    const double z = as241_tail<double>(sqrt(-log(r)));
+    return q < 0.0 ? -z : z;
+}
+
+__device__ __forceinline__ float inv_normal(double u, float)
+{
+    const double q = u - 0.5;
+    if (fabs(q) <= 0.425) return as241_central<float>((float)q);
+    double r = q < 0.0 ? u : 1.0 - u;      // exact fold in FP64
+    const float rf = fmaxf((float)r, 0x1p-64f);
+    const float z = as241_tail<float>(sqrtf(-__logf(rf)));
+    return q < 0.0 ? -z : z;
+}
+
+// ---------------------------------------------------------------------------
+// Elementary functions of the path arithmetic in the two precisions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double fexp(double x) { return exp(x); }
+__device__ __forceinline__ float fexp(float x) { return __expf(x); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fdiv(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ double fatan(double x) { return atan(x); }
+__device__ __forceinline__ float fatan(float x) { return atanf(x); }
+
+// ---------------------------------------------------------------------------
+// Deterministic reductions: butterfly over the 64 lanes (every lane ends with
+// the same total, summed in a fixed order), Neumaier compensated sums.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+struct Acc {
+    double s, c;
+};
+
+__device__ __forceinline__ void acc_add(Acc &a, double x)
+{
+    const double t = a.s + x;
+    if (fabs(a.s) >= fabs(x))
+        a.c += (a.s - t) + x;
+    else
+        a.c += (x - t) + a.s;
+    a.s = t;
+}
+
+}  // namespace rq

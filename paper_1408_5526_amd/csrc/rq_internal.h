@@ -1,0 +1,129 @@
+// rq_internal.h -- structures shared by the host side of the library and
+// its kernels.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rq {
+
+// Per-dimension constants (one entry per Halton base j).  The point index
+// range of a replication is cut in segments of S consecutive indices
+// (S a power of two); within a segment a lane only expands the low
+// L = min{L : p^L >= S} base-p digits of its index, the rest comes from a
+// per-(replication, segment, dimension) table built by the setup kernel.
+struct alignas(16) BaseEnt {
+    double pd;        // p as FP64
+    double invp_up;   // 1/p rounded toward +inf (exact floor(v/p) for v < 2^31)
+    double pDLd;      // p^{D-L} as FP64 (exact)
+    double Pd;        // P = p^D as FP64 (exact, <= 2^53)
+    uint64_t P;       // p^D
+    uint64_t pDL;     // p^{D-L}
+    uint32_t p;       // the prime
+    uint32_t D;       // digits carried
+    uint32_t L;       // low digits expanded per lane
+    uint32_t pL;      // p^L (< 2^30)
+    uint32_t perm_off;// offset of this base's permutation in the u16 table
+    uint32_t pad0, pad1, pad2;
+};
+static_assert(sizeof(BaseEnt) == 80, "BaseEnt layout");
+
+// Start decomposition of (replication, segment, dimension): index
+// base = (n + seg*S) mod P = hi * p^L + nlo.  A lane with local offset t
+// forms v = nlo + t (< 2 p^L), carry c = [v >= p^L]; its point is
+// R = rev_L(v - c p^L) * p^{D-L} + Rhi[c] with Rhi[c] the D-L digit
+// reversal of (hi + c) mod p^{D-L}.
+struct alignas(16) StartEnt {
+    double rhi0;      // Rhi[0] (exact integer < 2^53)
+    double rhi1;      // Rhi[1]
+    uint32_t nlo;
+    uint32_t hz;      // bit c set: (hi + c) mod p^{D-L} == 0 (leading-zero rule)
+    uint32_t pad0, pad1;
+};
+static_assert(sizeof(StartEnt) == 32, "StartEnt layout");
+
+constexpr int kBlock = 256;          // threads per pricing block (4 waves)
+constexpr int kWave = 64;
+
+// Flags (mirror of the public ones).
+constexpr int kStartZero = 1;
+constexpr int kPermRandom = 2;
+constexpr int kOutDigits = 4;
+
+// Arguments common to every kernel that generates points.
+struct SeqGeom {
+    const BaseEnt *base;     // [s]
+    const StartEnt *starts;  // [M][n_seg][s]
+    const uint16_t *perm;    // packed permutations or nullptr
+    int s;
+    int M;
+    int n_seg;
+    int perm_on;
+    int64_t N;
+    int64_t S;               // segment length (power of two)
+    int log2S;
+};
+
+struct SetupArgs {
+    BaseEnt *base_dev;       // read
+    StartEnt *starts;        // written [M][n_seg][s]
+    const uint16_t *perm;
+    uint64_t seed;
+    int64_t m_offset;
+    int s, M, n_seg;
+    int64_t S;
+    int flags;
+};
+
+// LIBOR model table, per forward n = 1..n_fwd (row n-1), kFwdRow doubles:
+//   a_n[0..2] (vol vector), c_n = -delta |a_n|^2 / 2, K_n (or NaN), L_n(0),
+//   has_caplet (1.0 / 0.0), pad
+constexpr int kFwdRow = 8;
+
+struct LmmArgs {
+    SeqGeom g;
+    const double *fwd;       // [n_fwd][kFwdRow]
+    double *partial;         // [M][n_blk][n_out]
+    double *per_path;        // [M][N][n_out] or nullptr
+    int n_fwd;
+    int n_out;
+    int n_blk;               // blocks per replication
+    double delta, sqrt_delta, num0;   // num0 = 1 + delta L_0(0)
+};
+
+struct MbsArgs {
+    SeqGeom g;
+    const double *ck;        // [months+1]: c_k
+    double *partial;         // [M][n_blk][1]
+    double *per_path;        // [M][N] or nullptr
+    int months;
+    int n_blk;
+    double i0, sig, K0, K1, K2, K3, K4, c;
+};
+
+struct ReduceArgs {
+    const double *partial;   // [M][n_blk][n_out]
+    double *theta;           // [M][n_out]
+    int M, n_blk, n_out;
+    double Nd;               // N as FP64
+};
+
+struct FinalizeArgs {
+    const double *theta;     // [M][n_out]
+    double *mean, *sd, *se;  // [n_out] (any may be null)
+    int M, n_out;
+};
+
+// Launchers (each returns the hipError_t of its launch).
+hipError_t launch_setup(const SetupArgs &a, hipStream_t st);
+hipError_t launch_sequence(const SeqGeom &g, int flags, void *out, hipStream_t st);
+hipError_t launch_lmm(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
+hipError_t launch_mbs(const MbsArgs &a, int fp32, hipStream_t st);
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);
+
+// Largest forward count of the compiled LIBOR kernels.
+constexpr int kMaxFwd = 80;
+
+}  // namespace rq

@@ -1,0 +1,122 @@
+// rq_mbs.hip -- Caflisch mortgage-backed-security pricing, one path per lane.
+//
+// Model (MBS section), months k = 1..K, z_k = Phi^{-1}(x_{k-1}):
+//   u_k = u_{k-1} / (1 + i_{k-1})            discount factor      (FP64)
+//   i_k = K0 exp(sigma z_k) i_{k-1}          monthly rate, K0 = exp(-sigma^2/2)
+//   w_k = K1 + K2 atan(K3 i_k + K4)          prepayment fraction
+//   PV += u_k c r_k ((1 - w_k) + w_k c_k)    cash flow m_k, discounted (FP64)
+//   r_{k+1} = r_k (1 - w_k)                  surviving fraction
+// The FP32 form keeps i, w, r and the normal in FP32; u, the cash-flow
+// product, PV and every reduction stay FP64.
+#include "rq_device.h"
+
+namespace rq {
+
+template <typename T, bool PERM>
+__global__ __launch_bounds__(kBlock) void mbs_kernel(MbsArgs a)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = tid / kWave;
+    const int m = blockIdx.x / a.n_blk;
+    const int blk = blockIdx.x - m * a.n_blk;
+    const int64_t i = (int64_t)blk * kBlock + tid;
+    const bool active = i < a.g.N;
+    const int seg = (int)(((int64_t)blk * kBlock) >> a.g.log2S);
+    const uint32_t t = (uint32_t)(i - ((int64_t)seg << a.g.log2S));
+    const StartEnt *__restrict__ st = a.g.starts + ((size_t)m * a.g.n_seg + seg) * a.g.s;
+    const double *__restrict__ ck = a.ck;
+
+    __shared__ double red[kBlock / kWave];
+
+    const T K0 = (T)a.K0, sig = (T)a.sig, K1 = (T)a.K1, K2 = (T)a.K2, K3 = (T)a.K3, K4 = (T)a.K4;
+    double u = 1.0, pv = 0.0;
+    T ir = (T)a.i0;
+    T r = T(1);
+#pragma unroll 1
+    for (int k = 1; k <= a.months; ++k) {
+        const int j = k - 1;
+        const PointCtx c = load_base(a.g.base, j);
+        const double x = radinv_x<PERM>(c, st + j, t, a.g.perm);
+        const T z = inv_normal(x, T(0));
+        u = u / (1.0 + (double)ir);
+        ir = K0 * fexp(sig * z) * ir;
+        const T w = K1 + K2 * fatan(K3 * ir + K4);
+        const double wd = (double)w;
+        pv += u * a.c * (double)r * ((1.0 - wd) + wd * ck[k]);
+        r = r * (T(1) - w);
+    }
+    pv = active ? pv : 0.0;
+    if (a.per_path && active) a.per_path[(size_t)m * (size_t)a.g.N + (size_t)i] = pv;
+    const double w = wave_sum(pv);
+    if (lane == 0) red[wave] = w;
+    __syncthreads();
+    if (tid == 0) {
+        double s = red[0];
+        s += red[1];
+        s += red[2];
+        s += red[3];
+        a.partial[(size_t)m * a.n_blk + blk] = s;
+    }
+}
+
+hipError_t launch_mbs(const MbsArgs &a, int fp32, hipStream_t st)
+{
+    const int64_t blocks = (int64_t)a.n_blk * a.g.M;
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    if (fp32) {
+        if (a.g.perm_on) hipLaunchKernelGGL((mbs_kernel<float, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((mbs_kernel<float, false>), grid, block, 0, st, a);
+    } else {
+        if (a.g.perm_on) hipLaunchKernelGGL((mbs_kernel<double, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((mbs_kernel<double, false>), grid, block, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reductions over blocks (theta) and over replications (RQ, sd, SE), each a
+// fixed-order Neumaier sum, so results are bit-reproducible run to run.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
+{
+    const int m = blockIdx.x;
+    for (int o = threadIdx.x; o < a.n_out; o += blockDim.x) {
+        Acc acc{0.0, 0.0};
+        const double *p = a.partial + (size_t)m * a.n_blk * a.n_out + o;
+        for (int b = 0; b < a.n_blk; ++b) acc_add(acc, p[(size_t)b * a.n_out]);
+        a.theta[(size_t)m * a.n_out + o] = (acc.s + acc.c) / a.Nd;
+    }
+}
+
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3(a.M), dim3(128), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= a.n_out) return;
+    Acc s{0.0, 0.0};
+    for (int m = 0; m < a.M; ++m) acc_add(s, a.theta[(size_t)m * a.n_out + o]);
+    const double mu = (s.s + s.c) / (double)a.M;
+    Acc q{0.0, 0.0};
+    for (int m = 0; m < a.M; ++m) {
+        const double d = a.theta[(size_t)m * a.n_out + o] - mu;
+        acc_add(q, __dmul_rn(d, d));
+    }
+    const double sd = a.M > 1 ? sqrt((q.s + q.c) / (double)(a.M - 1)) : __builtin_nan("");
+    if (a.mean) a.mean[o] = mu;
+    if (a.sd) a.sd[o] = sd;
+    if (a.se) a.se[o] = a.M > 1 ? sd / sqrt((double)a.M) : __builtin_nan("");
+}
+
+hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3((a.n_out + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace rq

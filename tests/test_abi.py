@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the public header declares, and rejects bad arguments before
+touching the device."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1408_5526_amd as rq
+import rqmc_inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "rqmc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rq_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rq.lib()
+    names = _declared()
+    assert {"rq_sequence", "rq_price_caplets", "rq_price_mbs", "rq_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert "gfx950" in rq.version()
+
+
+def test_workspace_sizes_and_validation():
+    lib = rq.lib()
+    n = lib.rq_sequence_workspace(10, 4096, 32, 0)
+    assert n >= 32 * 10 * 32
+    assert lib.rq_sequence_workspace(0, 4096, 32, 0) == 0
+    assert "s must be" in rq.last_error()
+    assert lib.rq_sequence_workspace(5000, 4096, 32, 0) == 0
+    assert "beyond" in rq.last_error()
+    assert lib.rq_sequence_workspace(1, 2 ** 53 + 1, 1, 0) == 0       # N > P_0 = 2^53
+    assert lib.rq_sequence_workspace(4, 100, 1, 64) == 0              # unknown flag
+
+
+def _call_caplets(model, N=256, M=2, ws_bytes=1 << 20, flags=0, prec=0, theta=1):
+    h = rq._LmmHost(model)
+    res = rq.rq_result(theta, 0, 0, 0)
+    return rq.lib().rq_price_caplets(C.byref(h.c), N, M, 1, 0, flags, prec, C.byref(res), None,
+                                     C.c_void_p(256), ws_bytes, None)
+
+
+def test_caplet_argument_errors_return_before_launch():
+    m = I.cfg1().model
+    bad = m.copy(); bad.L0[3] = -0.01
+    assert _call_caplets(bad) == rq.RQ_EINVAL and "L0[3]" in rq.last_error()
+    bad = m.copy(); bad.sigma[2] = -1.0
+    assert _call_caplets(bad) == rq.RQ_EINVAL
+    bad = I.small_lmm(4, 2); bad.loadings[1] *= 1.1
+    assert _call_caplets(bad) == rq.RQ_EINVAL and "norm" in rq.last_error()
+    big = I.lmm_curve80(n_fwd=80, n_factors=3)
+    big.n_fwd = 81
+    big.L0 = np.append(big.L0, 0.06); big.sigma = np.append(big.sigma, 0.1)
+    big.loadings = np.vstack([big.loadings, big.loadings[-1:]]); big.strike = np.append(big.strike, 0.06)
+    assert _call_caplets(big) == rq.RQ_EUNSUPPORTED
+    assert _call_caplets(m, N=0) == rq.RQ_EINVAL
+    assert _call_caplets(m, M=0) == rq.RQ_EINVAL
+    assert _call_caplets(m, theta=0) == rq.RQ_EINVAL
+    assert _call_caplets(m, flags=rq.OUT_DIGITS) == rq.RQ_EINVAL
+    assert _call_caplets(m, prec=7) == rq.RQ_EINVAL
+    assert _call_caplets(m, ws_bytes=16) == rq.RQ_EWORKSPACE and "needed" in rq.last_error()
+
+
+def test_mbs_argument_errors_return_before_launch():
+    p = rq._mbs_c(I.MbsParams(0, 0.007, 0.02, 0.01, -0.005, 10, 0.5))
+    res = rq.rq_result(1, 0, 0, 0)
+    st = rq.lib().rq_price_mbs(C.byref(p), 64, 1, 1, 0, 0, 0, C.byref(res), None, C.c_void_p(256), 1 << 20, None)
+    assert st == rq.RQ_EINVAL and "months" in rq.last_error()
+    p = rq._mbs_c(I.MbsParams(12, 0.007, -0.02, 0.01, -0.005, 10, 0.5))
+    st = rq.lib().rq_price_mbs(C.byref(p), 64, 1, 1, 0, 0, 0, C.byref(res), None, C.c_void_p(256), 1 << 20, None)
+    assert st == rq.RQ_EINVAL
+
+
+def test_misaligned_workspace_rejected():
+    st = rq.lib().rq_sequence(4, 64, 1, 1, 0, 0, C.c_void_p(1 << 20), C.c_void_p(257), 1 << 30, None)
+    assert st == rq.RQ_EWORKSPACE and "aligned" in rq.last_error()
+
+
+def test_python_api_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError, match="no GPU"):
+        rq.sequence(2, 8, 1, 1)
