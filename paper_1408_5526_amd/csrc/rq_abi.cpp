@@ -346,29 +346,36 @@ rq_status check_lmm(const rq_lmm_model *m)
     return RQ_OK;
 }
 
-// fwd table [n][8] FP64 then the same in FP32.
+// Forward tables: FP64 rows then FP32 rows (layout in rq_internal.h).
 std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
 {
     const int nf = m->n_fwd, d = m->n_factors;
+    const double log2e = 1.4426950408889634074;
     std::vector<double> t((size_t)nf * rq::kFwdRow, 0.0);
+    std::vector<float> f32((size_t)nf * rq::kFwdRow, 0.0f);
     for (int n = 1; n <= nf; ++n) {
         double *r = &t[(size_t)(n - 1) * rq::kFwdRow];
+        float *q = &f32[(size_t)(n - 1) * rq::kFwdRow];
         double an2 = 0.0;
         for (int f = 0; f < d; ++f) {
             const double a = m->sigma[n] * m->loadings[(size_t)(n - 1) * d + f];
             r[f] = a;
+            r[3 + f] = m->delta * a;
             an2 += a * a;
+            q[f] = (float)(log2e * a);
+            q[3 + f] = (float)(m->delta * a);
         }
-        r[3] = -0.5 * an2 * m->delta;
+        r[6] = -0.5 * an2 * m->delta;
+        r[7] = m->L0[n];
         const double K = m->strike[n - 1];
-        r[4] = std::isnan(K) ? 0.0 : K;
-        r[5] = m->L0[n];
-        r[6] = std::isnan(K) ? 0.0 : 1.0;
+        r[8] = std::isnan(K) ? 0.0 : K;
+        r[9] = std::isnan(K) ? 0.0 : 1.0;
+        q[6] = (float)(log2e * r[6]);
+        q[7] = (float)(m->delta * m->L0[n]);
     }
-    std::vector<uint8_t> out(t.size() * sizeof(double) + t.size() * sizeof(float));
+    std::vector<uint8_t> out(t.size() * sizeof(double) + f32.size() * sizeof(float));
     std::memcpy(out.data(), t.data(), t.size() * sizeof(double));
-    float *f32 = reinterpret_cast<float *>(out.data() + t.size() * sizeof(double));
-    for (size_t q = 0; q < t.size(); ++q) f32[q] = (float)t[q];
+    std::memcpy(out.data() + t.size() * sizeof(double), f32.data(), f32.size() * sizeof(float));
     return out;
 }
 

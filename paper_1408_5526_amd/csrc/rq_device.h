@@ -184,7 +184,11 @@ __device__ __forceinline__ float inv_normal(double u, float)
 __device__ __forceinline__ double fexp(double x) { return exp(x); }
 __device__ __forceinline__ float fexp(float x) { return __expf(x); }
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
-__device__ __forceinline__ float fdiv(float a, float b) { return __fdividef(a, b); }
+// a / b as a * rcp(b): v_rcp_f32 is accurate to 1 ulp
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }   // v_exp_f32
+__device__ __forceinline__ float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fatan(double x) { return atan(x); }
 __device__ __forceinline__ float fatan(float x) { return atanf(x); }
 
@@ -197,6 +201,30 @@ __device__ __forceinline__ double wave_sum(double v)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
+}
+
+// Sum 16 per-lane values over the wave with a transpose butterfly: at each
+// of the steps 32, 16, 8, 4 a lane keeps one half of its values, sends the
+// other half to its partner and adds what it receives, so 16 outputs cost
+// 8+4+2+1 exchanges plus two final ones instead of 16*6.  Afterwards lane l
+// with (l & 3) == 0 holds the wave total of output (l >> 2) & 15.  The
+// summation tree is fixed, so the result is deterministic.
+__device__ __forceinline__ double wave_sum16(double (&v)[16], int lane)
+{
+#pragma unroll
+    for (int h = 8, b = 32; h >= 1; h >>= 1, b >>= 1) {
+        const bool up = (lane & b) != 0;
+#pragma unroll
+        for (int q = 0; q < h; ++q) {
+            const double send = up ? v[q] : v[q + h];
+            const double keep = up ? v[q + h] : v[q];
+            v[q] = keep + __shfl_xor(send, b, kWave);
+        }
+    }
+    double r = v[0];
+    r += __shfl_xor(r, 2, kWave);
+    r += __shfl_xor(r, 1, kWave);
+    return r;
 }
 
 struct Acc {

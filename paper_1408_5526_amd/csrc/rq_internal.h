@@ -76,10 +76,21 @@ struct SetupArgs {
     int flags;
 };
 
-// LIBOR model table, per forward n = 1..n_fwd (row n-1), kFwdRow doubles:
-//   a_n[0..2] (vol vector), c_n = -delta |a_n|^2 / 2, K_n (or NaN), L_n(0),
-//   has_caplet (1.0 / 0.0), pad
-constexpr int kFwdRow = 8;
+// LIBOR model tables, per forward n = 1..n_fwd (row n-1), kFwdRow entries.
+// FP64 rows (doubles):
+//   [0..2] a_n            vol vector
+//   [3..5] delta a_n
+//   [6]    c_n = -delta |a_n|^2 / 2
+//   [7]    L_n(0)
+//   [8]    K_n (0 when there is no caplet)
+//   [9]    1 if forward n carries a caplet, else 0
+// FP32 rows (floats), log2 units:
+//   [0..2] log2(e) a_n
+//   [3..5] delta a_n
+//   [6]    log2(e) c_n
+//   [7]    delta L_n(0)
+// The FP32 table follows the FP64 one in the workspace.
+constexpr int kFwdRow = 12;
 
 struct LmmArgs {
     SeqGeom g;

@@ -6,31 +6,39 @@
 // discretised SDE, drift from pre-step values:
 //   g_n = delta L_n / (1 + delta L_n),  v += g_n a_n,  mu_n = a_n . v,
 //   L_n <- L_n exp(mu_n delta - delta |a_n|^2 / 2 + sqrt(delta) a_n . z_k).
-// After step k the caplet on L_{k+1} fixes and pays
-//   delta (L_{k+1} - K)^+ / (num * (1 + delta L_{k+1})),
-// num being the spot numeraire prod_{j<=k} (1 + delta L_j(T_j)) (FP64).
+// The kernel carries w = delta v + sqrt(delta) z_k instead of v, so that
+//   w += g_n (delta a_n),   exponent = a_n . w + c_n,   c_n = -delta|a_n|^2/2
+// (the same quantities regrouped: 2d fused multiply-adds per forward-step).
+// The caplet on L_n fixes at T_n and pays delta (L_n - K)^+ at T_{n+1},
+// discounted by the spot numeraire prod_{j<=n} (1 + delta L_j(T_j)) (FP64).
+// A forward is not touched after it fixes, so all payoffs are formed after
+// the time loop from the final state.
+//
+// FP32 form: the lane keeps X_n = log2(L_n / L_n(0)) instead of L_n, so the
+// drift term is delta L_n = (delta L_n(0)) 2^{X_n} (one v_exp_f32) and the
+// state stays O(1) in size: one step rounds ~3e-8 absolute instead of
+// ~1.2e-7 relative, and the exponential's error is not carried from step to
+// step.  Fixing values are formed in FP64, L_n(T_n) = L_n(0) 2^{X_n}.
 //
 // GPU mapping: a lane owns one path; the forward vector lives in registers.
 // The inner loop over forwards is unrolled to a compile-time capacity NFC so
-// that every L[n] is a fixed register; forwards that are dead (n <= k) or
-// beyond the model (n > n_fwd) are skipped by wave-uniform branches.  The
-// per-forward constants are wave-uniform and come through scalar loads.
-// Points are produced in registers from the replication's start table
-// (no point set is materialised).  Each step's caplet is summed over the
-// wave with a butterfly (fixed order), the four waves of a block are added
-// in a fixed order, and the block writes one partial per output: the
-// whole reduction is deterministic.
+// that every state element is a fixed register; forwards that are dead
+// (n < k) or beyond the model (n >= n_fwd) are skipped by one wave-uniform
+// branch each.  Per-forward constants are wave-uniform (scalar loads).
+// Points are produced in registers from the replication's start table (no
+// point set is materialised).  Payoffs are summed over the wave 16 outputs
+// at a time with a transpose butterfly, the four waves of a block in a fixed
+// order, and the block writes one partial per output: the whole reduction is
+// deterministic.
 #include "rq_device.h"
 
 namespace rq {
 
-template <typename T> struct FwdRow;
-template <> struct FwdRow<double> { using type = double; };
-template <> struct FwdRow<float> { using type = float; };
-
 template <int NFC, int D, typename T, bool PERM>
 __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a, const float *__restrict__ fwd32)
 {
+    static_assert(NFC % 16 == 0, "capacity must be a multiple of 16");
+    constexpr bool kF32 = sizeof(T) == 4;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = tid / kWave;
@@ -44,90 +52,106 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a, const float *__r
     const double *__restrict__ fwd = a.fwd;
     const int nf = a.n_fwd;
 
-    __shared__ double red[kBlock / kWave][NFC + 1];
+    __shared__ double red[kBlock / kWave][NFC];
+    __shared__ double tot[NFC];
 
-    // row of forward n: [a_0, a_1, a_2, c_n, K_n, L_n(0), has_caplet, -]
-    auto rowv = [&](int n, int c) -> T {
-        if constexpr (sizeof(T) == 8) return fwd[n * kFwdRow + c];
-        else return fwd32[n * kFwdRow + c];
-    };
+    auto r64 = [&](int n, int c) -> double { return fwd[n * kFwdRow + c]; };
+    auto r32 = [&](int n, int c) -> float { return fwd32[n * kFwdRow + c]; };
 
-    T L[NFC];
+    // state: FP32 X_n = log2(L_n/L_n(0)); FP64 L_n
+    T X[NFC];
 #pragma unroll
-    for (int n = 0; n < NFC; ++n) L[n] = n < nf ? rowv(n, 5) : T(0);
+    for (int n = 0; n < NFC; ++n) X[n] = kF32 ? T(0) : (n < nf ? T(r64(n, 7)) : T(0));
 
-    const T delta = (T)a.delta;
     const T sqd = (T)a.sqrt_delta;
-    double num = a.num0;
-    double book = 0.0;
-    double *pp = (a.per_path && active) ? a.per_path + ((size_t)m * (size_t)a.g.N + (size_t)i) * a.n_out
-                                        : nullptr;
+    const double delta = a.delta;
 
 #pragma unroll 1
     for (int k = 0; k < nf; ++k) {
-        T z[D];
+        T w[D];
 #pragma unroll
         for (int f = 0; f < D; ++f) {
             const int j = k * D + f;
             const PointCtx c = load_base(a.g.base, j);
             const double x = radinv_x<PERM>(c, st + j, t, a.g.perm);
-            z[f] = inv_normal(x, T(0));
+            w[f] = sqd * inv_normal(x, T(0));
         }
-        T v[D];
-#pragma unroll
-        for (int f = 0; f < D; ++f) v[f] = T(0);
-        T Lfix = T(0);
+        const unsigned alive = (unsigned)(nf - k);
 #pragma unroll
         for (int n = 0; n < NFC; ++n) {
-            if (n >= k && n < nf) {
-                T an[D];
+            if ((unsigned)(n - k) < alive) {
+                if constexpr (kF32) {
+                    const float dl = r32(n, 7) * fexp2(X[n]);
+                    const float g = dl * __builtin_amdgcn_rcpf(1.0f + dl);
 #pragma unroll
-                for (int f = 0; f < D; ++f) an[f] = rowv(n, f);
-                const T cn = rowv(n, 3);
-                const T Ln = L[n];
-                const T dl = delta * Ln;
-                const T g = fdiv(dl, T(1) + dl);
-                T mu = T(0), az = T(0);
+                    for (int f = 0; f < D; ++f) w[f] = ffma(g, r32(n, 3 + f), w[f]);
+                    // form the (small) step exponent first, then add it to the
+                    // O(1) state once: one rounding at the state's scale per step
+                    float e = r32(n, 6);
 #pragma unroll
-                for (int f = 0; f < D; ++f) v[f] = __builtin_fma(g, an[f], v[f]);
+                    for (int f = 0; f < D; ++f) e = ffma(r32(n, f), w[f], e);
+                    X[n] += e;
+                } else {
+                    const double dl = delta * X[n];
+                    const double g = dl / (1.0 + dl);
 #pragma unroll
-                for (int f = 0; f < D; ++f) {
-                    mu = __builtin_fma(an[f], v[f], mu);
-                    az = __builtin_fma(an[f], z[f], az);
+                    for (int f = 0; f < D; ++f) w[f] = ffma(g, r64(n, 3 + f), w[f]);
+                    double e = r64(n, 6);
+#pragma unroll
+                    for (int f = 0; f < D; ++f) e = ffma(r64(n, f), w[f], e);
+                    X[n] = X[n] * exp(e);
                 }
-                const T arg = __builtin_fma(mu, delta, __builtin_fma(sqd, az, cn));
-                const T Lnew = Ln * fexp(arg);
-                L[n] = Lnew;
-                if (n == k) Lfix = Lnew;
             }
         }
-        // caplet on forward k+1 fixes now (FP64 payoff and numeraire)
-        const double *row = fwd + k * kFwdRow;
-        const double Lf = (double)Lfix;
-        const double onep = 1.0 + a.delta * Lf;
-        double pay = 0.0;
-        if (row[6] != 0.0) {
-            const double ex = Lf - row[4];
-            pay = ex > 0.0 ? a.delta * ex / (num * onep) : 0.0;
+    }
+
+    // payoffs (FP64), 16 forwards at a time
+    double num = a.num0;
+    double book = 0.0;
+    double *pp = (a.per_path && active) ? a.per_path + ((size_t)m * (size_t)a.g.N + (size_t)i) * a.n_out
+                                        : nullptr;
+#pragma unroll
+    for (int c = 0; c < NFC / 16; ++c) {
+        if (c * 16 < nf) {
+            double P[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int n = c * 16 + q;
+                double pay = 0.0;
+                if (n < nf) {
+                    const double Lf = kF32 ? r64(n, 7) * exp2((double)X[n]) : (double)X[n];
+                    const double onep = 1.0 + delta * Lf;
+                    if (r64(n, 9) != 0.0) {
+                        const double ex = Lf - r64(n, 8);
+                        pay = ex > 0.0 ? delta * ex / (num * onep) : 0.0;
+                    }
+                    num *= onep;
+                    pay = active ? pay : 0.0;
+                    book += pay;
+                    if (pp) pp[n] = pay;
+                }
+                P[q] = pay;
+            }
+            const double s = wave_sum16(P, lane);
+            if ((lane & 3) == 0) red[wave][c * 16 + (lane >> 2)] = s;
         }
-        num *= onep;
-        pay = active ? pay : 0.0;
-        book += pay;
-        if (pp) pp[k] = pay;
-        const double w = wave_sum(pay);
-        if (lane == 0) red[wave][k] = w;
     }
     if (pp) pp[nf] = book;
-    const double wb = wave_sum(book);
-    if (lane == 0) red[wave][nf] = wb;
     __syncthreads();
     double *out = a.partial + ((size_t)m * a.n_blk + blk) * a.n_out;
-    for (int o = tid; o < a.n_out; o += kBlock) {
+    for (int o = tid; o < nf; o += kBlock) {
         double s = red[0][o];
         s += red[1][o];
         s += red[2][o];
         s += red[3][o];
+        tot[o] = s;
         out[o] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {   // the book: sum of the block's caplet totals, in order
+        double s = 0.0;
+        for (int o = 0; o < nf; ++o) s += tot[o];
+        out[nf] = s;
     }
 }
 
