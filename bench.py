@@ -79,6 +79,8 @@ def main(argv=None):
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-m-per-core", type=int, default=4)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB mebibytes device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -92,6 +94,14 @@ def main(argv=None):
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        n = args.copy_probe << 20
+        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n}), flush=True)
+        return 0
     c = I.cfg3()
     model, N, M, seed = c.model, c.N, c.M, c.seed
 

@@ -171,6 +171,14 @@ rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t s
                        int64_t m_offset, int flags, rq_precision prec, const rq_result *out,
                        double *per_path, void *ws, size_t ws_bytes, void *stream);
 
+/* inv_normal: the inverse standard normal CDF used on every path
+ * dimension, applied elementwise (a verification and utility entry).
+ *   u     device [n] FP64 points in [0, 1)
+ *   z     device [n], FP64 (RQ_FP64: Wichura's AS241) or FP32 (RQ_FP32: the
+ *         FP32 form of the pricing kernels, relative error ~2e-7)
+ * Values below 2^-64 in the fold min(u, 1-u) are clamped to it. */
+rq_status rq_inv_normal(int64_t n, const double *u, void *z, rq_precision prec, void *stream);
+
 /* Kernel timing instrumentation.  Between rq_timer_begin and rq_timer_end
  * every entry point records a pair of HIP events on its stream around its
  * main path kernel (the LIBOR or MBS pricing kernel, or the sequence

@@ -86,6 +86,8 @@ def lib():
     L.rq_price_mbs.argtypes = [C.POINTER(rq_mbs_params), C.c_int64, C.c_int, C.c_uint64, C.c_int64,
                                C.c_int, C.c_int, C.POINTER(rq_result), C.c_void_p, C.c_void_p,
                                C.c_size_t, C.c_void_p]
+    L.rq_inv_normal.restype = C.c_int
+    L.rq_inv_normal.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     L.rq_timer_begin.restype = C.c_int
     L.rq_timer_begin.argtypes = [C.c_int]
     L.rq_timer_end.restype = C.c_int
@@ -257,6 +259,19 @@ def price_mbs(params, N: int, M: int, seed: int, m_offset: int = 0, flags: int =
                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)))
     res.per_path = pp
     return res
+
+
+def inv_normal(u, precision="fp64"):
+    """Inverse standard normal CDF of a device FP64 tensor (elementwise)."""
+    torch = _torch()
+    if not u.is_cuda or u.dtype != torch.float64:
+        raise ValueError("u must be a float64 device tensor")
+    u = u.contiguous()
+    prec = _prec(precision)
+    z = torch.empty(u.shape, dtype=torch.float64 if prec == FP64 else torch.float32, device=u.device)
+    _check(lib().rq_inv_normal(u.numel(), C.c_void_p(u.data_ptr()), C.c_void_p(z.data_ptr()), prec,
+                               _stream(u.device)))
+    return z
 
 
 def timer_begin(max_launches: int = 1000) -> None:

@@ -193,6 +193,7 @@ rq_status build_point_tables(int s, const Geometry &g, uint64_t seed, int flags,
         b.invp_up = inv_up(p);
         b.pDLd = (double)b.pDL;
         b.Pd = (double)b.P;
+        b.invP = 1.0 / b.Pd;
         b.perm_off = off;
         if (flags & RQ_PERM_RANDOM) off += (uint32_t)p;
     }
@@ -441,6 +442,17 @@ extern "C" {
 const char *rq_last_error(void) { return g_err.c_str(); }
 
 const char *rq_version(void) { return "rqmc-mi355x 0.1 (gfx950)"; }
+
+rq_status rq_inv_normal(int64_t n, const double *u, void *z, rq_precision prec, void *stream)
+{
+    if (n < 0) return fail(RQ_EINVAL, "n must be >= 0");
+    if (n == 0) return RQ_OK;
+    if (!u || !z) return fail(RQ_EINVAL, "u and z must not be NULL");
+    if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
+    if ((n + 255) / 256 >= (1ll << 31)) return fail(RQ_ERANGE, "n too large for one launch");
+    RQ_HIP(rq::launch_inv_normal(n, u, z, prec == RQ_FP32, (hipStream_t)stream));
+    return RQ_OK;
+}
 
 rq_status rq_timer_begin(int max_launches)
 {

@@ -28,7 +28,7 @@ namespace rq {
 // zeros too; they are exactly the digits met once the remaining value is 0.
 // ---------------------------------------------------------------------------
 struct PointCtx {
-    double pd, invp, pDLd, Pd;
+    double pd, invp, pDLd, Pd, invP;
     uint32_t L, pL, perm_off;
 };
 
@@ -40,6 +40,7 @@ __device__ __forceinline__ PointCtx load_base(const BaseEnt *__restrict__ base, 
     c.invp = b->invp_up;
     c.pDLd = b->pDLd;
     c.Pd = b->Pd;
+    c.invP = b->invP;
     c.L = b->L;
     c.pL = b->pL;
     c.perm_off = b->perm_off;
@@ -78,11 +79,14 @@ __device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt *__
     return __builtin_fma(R, c.pDLd, rhi);
 }
 
-template <bool PERM>
+// The point RN(R / P).  EXACT = false forms R * RN(1/P) instead, within
+// two ulps of it (used where the point only feeds FP32 arithmetic).
+template <bool PERM, bool EXACT = true>
 __device__ __forceinline__ double radinv_x(const PointCtx &c, const StartEnt *__restrict__ e,
                                            uint32_t t, const uint16_t *__restrict__ perm)
 {
-    return radinv_R<PERM>(c, e, t, perm) / c.Pd;
+    const double R = radinv_R<PERM>(c, e, t, perm);
+    return EXACT ? R / c.Pd : R * c.invP;
 }
 
 // ---------------------------------------------------------------------------
@@ -168,14 +172,50 @@ __device__ __forceinline__ double inv_normal(double u, double)
     return q < 0.0 ? -z : z;
 }
 
+// FP32 form (a fit of our own, generated by fit_inv_normal.py, after the
+// shape of Giles 2011): x = 2u - 1, w = -ln(4u(1-u)),
+//   Phi^{-1}(u) = x P(w - 2.5) for w < 5 (~99.7% of points), else
+//   Phi^{-1}(u) = x Q(sqrt(w) - 3), down to the clamp u(1-u) >= 2^-64.
+// u(1-u) and x are formed in FP64 from the FP64 point; the rest is FP32.
+// Relative error ~1e-8 of the fits plus float rounding (~2e-7).  The tail
+// branch runs only in waves that hold a tail point (~20% of waves).
 __device__ __forceinline__ float inv_normal(double u, float)
 {
-    const double q = u - 0.5;
-    if (fabs(q) <= 0.425) return as241_central<float>((float)q);
-    double r = q < 0.0 ? u : 1.0 - u;      // exact fold in FP64
-    const float rf = fmaxf((float)r, 0x1p-64f);
-    const float z = as241_tail<float>(sqrtf(-__logf(rf)));
-    return q < 0.0 ? -z : z;
+    const double p = u * (1.0 - u);
+    const float pf = fmaxf((float)p, 0x1p-64f);
+    const float w = __builtin_fmaf(__builtin_amdgcn_logf(pf), -0.693147180559945309f,
+                                   -1.38629436111989062f);   // -ln(4 p)
+    const float x = (float)__builtin_fma(2.0, u, -1.0);
+    float r;
+    if (w < 5.0f) {
+        const float t = w - 2.5f;
+        r = -1.2261584636519274e-08f;
+        r = __builtin_fmaf(r, t, 3.278690030583675e-08f);
+        r = __builtin_fmaf(r, t, 6.569200650119456e-07f);
+        r = __builtin_fmaf(r, t, -4.896187874692259e-06f);
+        r = __builtin_fmaf(r, t, -7.0085679908515885e-06f);
+        r = __builtin_fmaf(r, t, 0.0003087827062699944f);
+        r = __builtin_fmaf(r, t, -0.0017716623842716217f);
+        r = __builtin_fmaf(r, t, -0.0059077139012515545f);
+        r = __builtin_fmaf(r, t, 0.3488020598888397f);
+        r = __builtin_fmaf(r, t, 2.1233134269714355f);
+    } else {
+        const float t = __builtin_sqrtf(w) - 3.0f;
+        r = -3.145217988276272e-07f;
+        r = __builtin_fmaf(r, t, 5.651296305586584e-06f);
+        r = __builtin_fmaf(r, t, -4.1833809518720955e-05f);
+        r = __builtin_fmaf(r, t, 0.00015798278036527336f);
+        r = __builtin_fmaf(r, t, -0.00026979981339536607f);
+        r = __builtin_fmaf(r, t, -0.00016467731620650738f);
+        r = __builtin_fmaf(r, t, 0.001944091753102839f);
+        r = __builtin_fmaf(r, t, -0.004991183523088694f);
+        r = __builtin_fmaf(r, t, 0.008097918704152107f);
+        r = __builtin_fmaf(r, t, -0.010832239873707294f);
+        r = __builtin_fmaf(r, t, 0.013349912129342556f);
+        r = __builtin_fmaf(r, t, 1.416584849357605f);
+        r = __builtin_fmaf(r, t, 4.006434440612793f);
+    }
+    return x * r;
 }
 
 // ---------------------------------------------------------------------------

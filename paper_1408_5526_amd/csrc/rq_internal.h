@@ -25,7 +25,8 @@ struct alignas(16) BaseEnt {
     uint32_t L;       // low digits expanded per lane
     uint32_t pL;      // p^L (< 2^30)
     uint32_t perm_off;// offset of this base's permutation in the u16 table
-    uint32_t pad0, pad1, pad2;
+    uint32_t pad0;
+    double invP;      // RN(1/P)
 };
 static_assert(sizeof(BaseEnt) == 80, "BaseEnt layout");
 
@@ -133,6 +134,7 @@ hipError_t launch_lmm(const LmmArgs &a, int n_factors, int fp32, hipStream_t st)
 hipError_t launch_mbs(const MbsArgs &a, int fp32, hipStream_t st);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);
+hipError_t launch_inv_normal(int64_t n, const double *u, void *z, int fp32, hipStream_t st);
 
 // Largest forward count of the compiled LIBOR kernels.
 constexpr int kMaxFwd = 80;

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a, const float *__r
         for (int f = 0; f < D; ++f) {
             const int j = k * D + f;
             const PointCtx c = load_base(a.g.base, j);
-            const double x = radinv_x<PERM>(c, st + j, t, a.g.perm);
+            const double x = radinv_x<PERM, sizeof(T) == 8>(c, st + j, t, a.g.perm);
             w[f] = sqd * inv_normal(x, T(0));
         }
         const unsigned alive = (unsigned)(nf - k);

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kBlock) void mbs_kernel(MbsArgs a)
     for (int k = 1; k <= a.months; ++k) {
         const int j = k - 1;
         const PointCtx c = load_base(a.g.base, j);
-        const double x = radinv_x<PERM>(c, st + j, t, a.g.perm);
+        const double x = radinv_x<PERM, sizeof(T) == 8>(c, st + j, t, a.g.perm);
         const T z = inv_normal(x, T(0));
         u = u / (1.0 + (double)ir);
         ir = K0 * fexp(sig * z) * ir;
@@ -116,6 +116,25 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a)
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(finalize_kernel, dim3((a.n_out + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// Elementwise inverse normal (verification / utility entry).
+template <typename T>
+__global__ __launch_bounds__(256) void inv_normal_kernel(int64_t n, const double *__restrict__ u,
+                                                         T *__restrict__ z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = inv_normal(u[i], T(0));
+}
+
+hipError_t launch_inv_normal(int64_t n, const double *u, void *z, int fp32, hipStream_t st)
+{
+    const int64_t blocks = (n + 255) / 256;
+    if (fp32)
+        hipLaunchKernelGGL(inv_normal_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, n, u, (float *)z);
+    else
+        hipLaunchKernelGGL(inv_normal_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, n, u, (double *)z);
     return hipGetLastError();
 }
 

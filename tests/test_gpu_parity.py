@@ -100,6 +100,36 @@ def test_sequence_many_segments_sampled():
 
 
 # ---------------------------------------------------------------------------
+# inverse normal
+# ---------------------------------------------------------------------------
+def _inv_normal_points():
+    rng = np.random.default_rng(3)
+    return np.concatenate([rng.random(200000), 10.0 ** rng.uniform(-19, -1, 20000),
+                           1 - 10.0 ** rng.uniform(-16, -1, 20000),
+                           [0.0, 2.0 ** -64, 2.0 ** -70, 0.5, 0.0017, 0.00169, 0.9983, 0.075, 0.925]])
+
+
+def test_inv_normal_fp64_matches_oracle():
+    import torch
+    _say("inv_normal fp64")
+    u = _inv_normal_points()
+    z = _np(rq.inv_normal(torch.as_tensor(u, device="cuda")))
+    zo = O.ppnd16(u)
+    assert np.allclose(z, zo, rtol=2e-15, atol=1e-300)
+
+
+def test_inv_normal_fp32_error_bound():
+    import torch
+    _say("inv_normal fp32")
+    u = _inv_normal_points()
+    z = _np(rq.inv_normal(torch.as_tensor(u, device="cuda"), "fp32")).astype(np.float64)
+    zo = O.ppnd16(u)
+    err = np.abs(z - zo) / np.maximum(np.abs(zo), 1e-3)
+    _say("fp32 inverse normal max rel err", float(err.max()))
+    assert err.max() < 5e-7
+
+
+# ---------------------------------------------------------------------------
 # LIBOR market model
 # ---------------------------------------------------------------------------
 def _one_fwd():
