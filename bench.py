@@ -37,6 +37,35 @@ FLOPS_PER_PATH_LMM80 = 93_040
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 
 
+def _kernel_source_hash() -> str:
+    import hashlib
+    m = hashlib.sha256()
+    for name in ("rq_lmm.hip", "rq_device.h", "rq_internal.h"):
+        with open(os.path.join(ROOT, "paper_1408_5526_amd", "csrc", name), "rb") as f:
+            m.update(f.read())
+    return m.hexdigest()[:16]
+
+
+def _traffic_bytes():
+    """HBM bytes per launch of the FP32 80-forward kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE measurement, scaled by the copy-probe
+    factors -- or None when the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", "lmm80_3f_fp32_traffic.txt")
+    try:
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if line.strip() and not line.startswith("#"):
+                    k, v = line.split()
+                    kv[k] = v
+        if kv.get("source_hash") != _kernel_source_hash():
+            return None
+        return (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
+                float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def _time_steps(fn, steps: int, warmup: int):
     import torch
     import paper_1408_5526_amd as rq
@@ -96,9 +125,12 @@ def main(argv=None):
     torch.cuda.set_device(dev)
     if args.copy_probe:
         n = args.copy_probe << 20
-        src = torch.ones(n, dtype=torch.uint8, device=dev)
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        scratch = torch.empty(n // 4, dtype=torch.float32, device=dev)
+        scratch.fill_(2.0)          # evicts src from the caches
+        torch.cuda.synchronize()
+        dst.copy_(src)              # reads n bytes, writes n bytes
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n}), flush=True)
         return 0
@@ -150,7 +182,8 @@ def main(argv=None):
                    "N": N, "M": M, "seed": seed, "precision": head, "greeks": False},
         "greeks_per_s": None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": _traffic_bytes() if dtype == "f32" else None,
                      "kernel": "lmm_kernel<80,3,%s>" % ("float" if dtype == "f32" else "double"),
                      "kernel_ms": kms},
     }

@@ -347,16 +347,20 @@ rq_status check_lmm(const rq_lmm_model *m)
     return RQ_OK;
 }
 
+// Table rows: n_fwd rounded up to whole groups.
+int lmm_rows(int nf) { return (nf + rq::kGrp - 1) / rq::kGrp * rq::kGrp; }
+
 // Forward tables: FP64 rows then FP32 rows (layout in rq_internal.h).
 std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
 {
     const int nf = m->n_fwd, d = m->n_factors;
+    const int nrow = lmm_rows(nf);
     const double log2e = 1.4426950408889634074;
-    std::vector<double> t((size_t)nf * rq::kFwdRow, 0.0);
-    std::vector<float> f32((size_t)nf * rq::kFwdRow, 0.0f);
+    std::vector<double> t((size_t)nrow * rq::kFwdRow, 0.0);
+    std::vector<float> f32((size_t)nrow * rq::kRow32, 0.0f);
     for (int n = 1; n <= nf; ++n) {
         double *r = &t[(size_t)(n - 1) * rq::kFwdRow];
-        float *q = &f32[(size_t)(n - 1) * rq::kFwdRow];
+        float *q = &f32[(size_t)(n - 1) * rq::kRow32];
         double an2 = 0.0;
         for (int f = 0; f < d; ++f) {
             const double a = m->sigma[n] * m->loadings[(size_t)(n - 1) * d + f];
@@ -372,7 +376,7 @@ std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
         r[8] = std::isnan(K) ? 0.0 : K;
         r[9] = std::isnan(K) ? 0.0 : 1.0;
         q[6] = (float)(log2e * r[6]);
-        q[7] = (float)(m->delta * m->L0[n]);
+        q[7] = (float)std::log2(m->delta * m->L0[n]);
     }
     std::vector<uint8_t> out(t.size() * sizeof(double) + f32.size() * sizeof(float));
     std::memcpy(out.data(), t.data(), t.size() * sizeof(double));
@@ -529,7 +533,7 @@ size_t rq_caplets_workspace(const rq_lmm_model *model, int64_t N, int M, int fla
     const int s = model->n_fwd * model->n_factors;
     if (check_common(s, N, M, flags, 0, g) != RQ_OK) return 0;
     (void)prec;
-    const size_t mb = (size_t)model->n_fwd * rq::kFwdRow * (sizeof(double) + sizeof(float));
+    const size_t mb = (size_t)lmm_rows(model->n_fwd) * (rq::kFwdRow * sizeof(double) + rq::kRow32 * sizeof(float));
     const size_t pb = (size_t)M * lmm_blocks(N) * (model->n_fwd + 1) * sizeof(double);
     return layout(s, g, M, flags, mb, pb).total;
 }
@@ -560,6 +564,7 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     rq::LmmArgs a;
     a.g = seq_geom(L, g, w, s, M, N, flags);
     a.fwd = reinterpret_cast<const double *>(w + L.model);
+    a.fwd32 = reinterpret_cast<const float *>(w + L.model + (size_t)lmm_rows(model->n_fwd) * rq::kFwdRow * sizeof(double));
     a.partial = reinterpret_cast<double *>(w + L.partial);
     a.per_path = per_path;
     a.n_fwd = model->n_fwd;

@@ -47,7 +47,10 @@ __device__ __forceinline__ PointCtx load_base(const BaseEnt *__restrict__ base, 
     return c;
 }
 
-// R of the lane's point as an exact FP64 integer.
+// R of the lane's point as an exact FP64 integer.  The carry picks the high
+// part as Rhi[0] + c (Rhi[1] - Rhi[0]): arithmetic on two scalars instead of
+// a per-lane selected load.  Digits go two at a time to keep the loop free
+// of register shuffles.
 template <bool PERM>
 __device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt *__restrict__ e,
                                            uint32_t t, const uint16_t *__restrict__ perm)
@@ -55,15 +58,22 @@ __device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt *__
     uint32_t vi = e->nlo + t;                 // < 2 p^L <= 2^31
     const bool carry = vi >= c.pL;
     vi -= carry ? c.pL : 0u;
-    const double rhi = carry ? e->rhi1 : e->rhi0;
+    const double rhi = __builtin_fma(carry ? 1.0 : 0.0, e->drhi, e->rhi0);
     double v = (double)vi;
     double R = 0.0;
     if (!PERM) {
-        for (uint32_t q = 0; q < c.L; ++q) {
-            const double qt = __builtin_trunc(v * c.invp);
-            const double a = __builtin_fma(-qt, c.pd, v);
-            R = __builtin_fma(R, c.pd, a);
-            v = qt;
+        uint32_t q = 0;
+        for (; q + 2 <= c.L; q += 2) {
+            const double q1 = __builtin_trunc(v * c.invp);
+            const double a1 = __builtin_fma(-q1, c.pd, v);
+            const double q2 = __builtin_trunc(q1 * c.invp);
+            const double a2 = __builtin_fma(-q2, c.pd, q1);
+            R = __builtin_fma(__builtin_fma(R, c.pd, a1), c.pd, a2);
+            v = q2;
+        }
+        if (q < c.L) {
+            const double q1 = __builtin_trunc(v * c.invp);
+            R = __builtin_fma(R, c.pd, __builtin_fma(-q1, c.pd, v));
         }
     } else {
         const bool hz = (e->hz >> (carry ? 1 : 0)) & 1u;
@@ -200,7 +210,7 @@ __device__ __forceinline__ float inv_normal(double u, float)
         r = __builtin_fmaf(r, t, 0.3488020598888397f);
         r = __builtin_fmaf(r, t, 2.1233134269714355f);
     } else {
-        const float t = __builtin_sqrtf(w) - 3.0f;
+        const float t = __builtin_amdgcn_sqrtf(w) - 3.0f;   // v_sqrt_f32
         r = -3.145217988276272e-07f;
         r = __builtin_fmaf(r, t, 5.651296305586584e-06f);
         r = __builtin_fmaf(r, t, -4.1833809518720955e-05f);

@@ -37,7 +37,7 @@ static_assert(sizeof(BaseEnt) == 80, "BaseEnt layout");
 // reversal of (hi + c) mod p^{D-L}.
 struct alignas(16) StartEnt {
     double rhi0;      // Rhi[0] (exact integer < 2^53)
-    double rhi1;      // Rhi[1]
+    double drhi;      // Rhi[1] - Rhi[0] (exact)
     uint32_t nlo;
     uint32_t hz;      // bit c set: (hi + c) mod p^{D-L} == 0 (leading-zero rule)
     uint32_t pad0, pad1;
@@ -77,25 +77,27 @@ struct SetupArgs {
     int flags;
 };
 
-// LIBOR model tables, per forward n = 1..n_fwd (row n-1), kFwdRow entries.
-// FP64 rows (doubles):
+// LIBOR model tables, per forward n = 1..n_fwd (row n-1), kFwdRow doubles:
 //   [0..2] a_n            vol vector
 //   [3..5] delta a_n
 //   [6]    c_n = -delta |a_n|^2 / 2
 //   [7]    L_n(0)
 //   [8]    K_n (0 when there is no caplet)
 //   [9]    1 if forward n carries a caplet, else 0
-// FP32 rows (floats), log2 units:
+// followed by the FP32 rows, kRow32 floats per forward, log2 units:
 //   [0..2] log2(e) a_n
 //   [3..5] delta a_n
 //   [6]    log2(e) c_n
-//   [7]    delta L_n(0)
-// The FP32 table follows the FP64 one in the workspace.
+//   [7]    log2(delta L_n(0))
+// Both tables are padded with zero rows to a multiple of kGrp forwards.
 constexpr int kFwdRow = 12;
+constexpr int kRow32 = 8;
+constexpr int kGrp = 4;   // forwards per branch-free group of the LIBOR kernel
 
 struct LmmArgs {
     SeqGeom g;
     const double *fwd;       // [n_fwd][kFwdRow]
+    const float *fwd32;      // [n_fwd][kRow32]
     double *partial;         // [M][n_blk][n_out]
     double *per_path;        // [M][N][n_out] or nullptr
     int n_fwd;

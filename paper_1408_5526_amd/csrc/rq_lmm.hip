@@ -14,11 +14,15 @@
 // A forward is not touched after it fixes, so all payoffs are formed after
 // the time loop from the final state.
 //
-// FP32 form: the lane keeps X_n = log2(L_n / L_n(0)) instead of L_n, so the
-// drift term is delta L_n = (delta L_n(0)) 2^{X_n} (one v_exp_f32) and the
-// state stays O(1) in size: one step rounds ~3e-8 absolute instead of
-// ~1.2e-7 relative, and the exponential's error is not carried from step to
-// step.  Fixing values are formed in FP64, L_n(T_n) = L_n(0) 2^{X_n}.
+// FP32 form: the lane keeps X_n = log2(L_n / L_n(0)).  With the constant
+// l_n = log2(delta L_n(0)) the drift factor is
+//   g_n = 1 / (1 + 2^{-(X_n + l_n)})
+// (one add, one v_exp_f32, one add, one v_rcp_f32), and the step is
+//   X_n += log2(e) (a_n . w + c_n),
+// the (small) increment being formed before it is added, so the O(1) state
+// rounds once per step at its own scale (~3e-8) and the exponential's error
+// is not carried from step to step.  Fixing values are formed in FP64,
+// L_n(T_n) = L_n(0) 2^{X_n}.
 //
 // GPU mapping: a lane owns one path; the forward vector lives in registers.
 // The inner loop over forwards is unrolled to a compile-time capacity NFC so
@@ -34,8 +38,9 @@
 
 namespace rq {
 
+
 template <int NFC, int D, typename T, bool PERM>
-__global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a, const float *__restrict__ fwd32)
+__global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a)
 {
     static_assert(NFC % 16 == 0, "capacity must be a multiple of 16");
     constexpr bool kF32 = sizeof(T) == 4;
@@ -56,9 +61,8 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a, const float *__r
     __shared__ double tot[NFC];
 
     auto r64 = [&](int n, int c) -> double { return fwd[n * kFwdRow + c]; };
-    auto r32 = [&](int n, int c) -> float { return fwd32[n * kFwdRow + c]; };
 
-    // state: FP32 X_n = log2(L_n/L_n(0)); FP64 L_n
+    // state: FP32 X_n = log2(L_n / L_n(0)); FP64 L_n
     T X[NFC];
 #pragma unroll
     for (int n = 0; n < NFC; ++n) X[n] = kF32 ? T(0) : (n < nf ? T(r64(n, 7)) : T(0));
@@ -76,30 +80,59 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a, const float *__r
             const double x = radinv_x<PERM, sizeof(T) == 8>(c, st + j, t, a.g.perm);
             w[f] = sqd * inv_normal(x, T(0));
         }
+        // One forward-step of forward n.  FP32: on = 1 for a forward alive in
+        // this step, 0 otherwise; a dead forward's drift factor and state
+        // update are multiplied by 0, so a group of kGrp forwards runs as one
+        // branch-free block whose independent drift factors overlap with the
+        // chain through w.  Wholly dead groups are skipped.  (FP64 branches
+        // per forward and ignores `on`.)
+        auto body = [&](int n, T on) __attribute__((always_inline)) {
+            if constexpr (kF32) {
+                const float *q = a.fwd32 + n * kRow32;
+                const float s = X[n] + q[7];            // log2(delta L_n)
+                const float g = __builtin_amdgcn_rcpf(1.0f + fexp2(-s)) * on;
+#pragma unroll
+                for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
+                // form the (small) step increment first, then add it to the
+                // O(1) state once: one rounding at the state's scale per step
+                float e = q[0] * w[0];
+#pragma unroll
+                for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
+                X[n] = ffma(e + q[6], on, X[n]);
+            } else {
+                const double dl = delta * X[n];
+                const double g = dl / (1.0 + dl);
+#pragma unroll
+                for (int f = 0; f < D; ++f) w[f] = ffma(g, r64(n, 3 + f), w[f]);
+                double e = r64(n, 6);
+#pragma unroll
+                for (int f = 0; f < D; ++f) e = ffma(r64(n, f), w[f], e);
+                X[n] = X[n] * exp(e);
+            }
+        };
         const unsigned alive = (unsigned)(nf - k);
+        if constexpr (!kF32) {
+            // FP64: one uniform branch per forward (its exp and division are
+            // too costly to spend on dead forwards)
 #pragma unroll
-        for (int n = 0; n < NFC; ++n) {
-            if ((unsigned)(n - k) < alive) {
-                if constexpr (kF32) {
-                    const float dl = r32(n, 7) * fexp2(X[n]);
-                    const float g = dl * __builtin_amdgcn_rcpf(1.0f + dl);
+            for (int n = 0; n < NFC; ++n)
+                if ((unsigned)(n - k) < alive) body(n, 1.0);
+            continue;
+        }
 #pragma unroll
-                    for (int f = 0; f < D; ++f) w[f] = ffma(g, r32(n, 3 + f), w[f]);
-                    // form the (small) step exponent first, then add it to the
-                    // O(1) state once: one rounding at the state's scale per step
-                    float e = r32(n, 6);
+        for (int gq = 0; gq < NFC / kGrp; ++gq) {
+            const int n0 = gq * kGrp;
+            if (n0 + kGrp > k && n0 < nf) {
 #pragma unroll
-                    for (int f = 0; f < D; ++f) e = ffma(r32(n, f), w[f], e);
-                    X[n] += e;
-                } else {
-                    const double dl = delta * X[n];
-                    const double g = dl / (1.0 + dl);
-#pragma unroll
-                    for (int f = 0; f < D; ++f) w[f] = ffma(g, r64(n, 3 + f), w[f]);
-                    double e = r64(n, 6);
-#pragma unroll
-                    for (int f = 0; f < D; ++f) e = ffma(r64(n, f), w[f], e);
-                    X[n] = X[n] * exp(e);
+                for (int u = 0; u < kGrp; ++u) {
+                    // wave-uniform 0/1, formed as bits so that it stays scalar
+                    T on;
+                    if constexpr (kF32)
+                        on = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                 (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u));
+                    else
+                        on = (unsigned)(n0 + u - k) < alive ? 1.0 : 0.0;
+                    body(n0 + u, on);
                 }
             }
         }
@@ -156,37 +189,35 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a, const float *__r
 }
 
 template <int NFC, int D, typename T>
-static hipError_t launch_t(const LmmArgs &a, const float *fwd32, hipStream_t st)
+static hipError_t launch_t(const LmmArgs &a, hipStream_t st)
 {
     const int64_t blocks = (int64_t)a.n_blk * a.g.M;
     if (a.g.perm_on)
-        hipLaunchKernelGGL((lmm_kernel<NFC, D, T, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a, fwd32);
+        hipLaunchKernelGGL((lmm_kernel<NFC, D, T, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
     else
-        hipLaunchKernelGGL((lmm_kernel<NFC, D, T, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a, fwd32);
+        hipLaunchKernelGGL((lmm_kernel<NFC, D, T, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
 template <int D, typename T>
-static hipError_t launch_d(const LmmArgs &a, const float *fwd32, hipStream_t st)
+static hipError_t launch_d(const LmmArgs &a, hipStream_t st)
 {
-    if (a.n_fwd <= 16) return launch_t<16, D, T>(a, fwd32, st);
-    if (a.n_fwd <= 32) return launch_t<32, D, T>(a, fwd32, st);
-    if (a.n_fwd <= 48) return launch_t<48, D, T>(a, fwd32, st);
-    if (a.n_fwd <= 64) return launch_t<64, D, T>(a, fwd32, st);
-    return launch_t<80, D, T>(a, fwd32, st);
+    if (a.n_fwd <= 16) return launch_t<16, D, T>(a, st);
+    if (a.n_fwd <= 32) return launch_t<32, D, T>(a, st);
+    if (a.n_fwd <= 48) return launch_t<48, D, T>(a, st);
+    if (a.n_fwd <= 64) return launch_t<64, D, T>(a, st);
+    return launch_t<80, D, T>(a, st);
 }
 
 hipError_t launch_lmm(const LmmArgs &a, int n_factors, int fp32, hipStream_t st)
 {
-    // the FP32 table follows the FP64 one in the workspace
-    const float *fwd32 = reinterpret_cast<const float *>(a.fwd + (size_t)a.n_fwd * kFwdRow);
     switch (n_factors * 2 + (fp32 ? 1 : 0)) {
-    case 2: return launch_d<1, double>(a, fwd32, st);
-    case 3: return launch_d<1, float>(a, fwd32, st);
-    case 4: return launch_d<2, double>(a, fwd32, st);
-    case 5: return launch_d<2, float>(a, fwd32, st);
-    case 6: return launch_d<3, double>(a, fwd32, st);
-    case 7: return launch_d<3, float>(a, fwd32, st);
+    case 2: return launch_d<1, double>(a, st);
+    case 3: return launch_d<1, float>(a, st);
+    case 4: return launch_d<2, double>(a, st);
+    case 5: return launch_d<2, float>(a, st);
+    case 6: return launch_d<3, double>(a, st);
+    case 7: return launch_d<3, float>(a, st);
     default: return hipErrorInvalidValue;
     }
 }

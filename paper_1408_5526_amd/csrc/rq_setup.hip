@@ -68,8 +68,10 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a)
     uint64_t h1 = hi + 1;
     if (h1 >= b.pDL) h1 -= b.pDL;
     StartEnt e;
-    e.rhi0 = (double)reverse_high(h0, b.p, nd, sg);
-    e.rhi1 = (double)reverse_high(h1, b.p, nd, sg);
+    const uint64_t r0 = reverse_high(h0, b.p, nd, sg);
+    const uint64_t r1 = reverse_high(h1, b.p, nd, sg);
+    e.rhi0 = (double)r0;
+    e.drhi = (double)(int64_t)(r1 - r0);   // |r1 - r0| < 2^53: exact
     e.nlo = nlo;
     e.hz = (h0 == 0 ? 1u : 0u) | (h1 == 0 ? 2u : 0u);
     e.pad0 = e.pad1 = 0;
