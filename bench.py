@@ -34,23 +34,34 @@ if ROOT not in sys.path:
 # add/mul = 1, each special function = 1): 3,240 forward-steps x 26, 240
 # inverse normals x 32, 80 payoffs x 12, 240 point divisions.
 FLOPS_PER_PATH_LMM80 = 93_040
+# Price + 161 Greeks per path: the forward pass above, the adjoint of each of
+# the 3,240 forward-steps (42 flops: the suffix sum of the w adjoint, the
+# drift-factor adjoint and its derivative, the vega terms, rewinding w), the
+# 240 normals regenerated for the reverse sweep (33 each) and the adjoint of
+# the 80 payoffs (20 each).
+FLOPS_PER_PATH_LMM80_GREEKS = 93_040 + 3_240 * 42 + 240 * 33 + 80 * 20
+N_GREEKS_LMM80 = 2 * 80 + 1
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 
 
-def _kernel_source_hash() -> str:
+ADJ_SOURCES = ("rq_lmm_adj.h", "rq_lmm_adj32.hip", "rq_device.h", "rq_internal.h")
+PRICE_SOURCES = ("rq_lmm.hip", "rq_device.h", "rq_internal.h")
+
+
+def _kernel_source_hash(names) -> str:
     import hashlib
     m = hashlib.sha256()
-    for name in ("rq_lmm.hip", "rq_device.h", "rq_internal.h"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_1408_5526_amd", "csrc", name), "rb") as f:
             m.update(f.read())
     return m.hexdigest()[:16]
 
 
-def _traffic_bytes():
-    """HBM bytes per launch of the FP32 80-forward kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE measurement, scaled by the copy-probe
-    factors -- or None when the kernel source has changed since."""
-    path = os.path.join(ROOT, "profiles", "lmm80_3f_fp32_traffic.txt")
+def _traffic_bytes(profile: str, sources):
+    """HBM bytes per launch of a kernel from a committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE measurement, scaled by the copy-probe factors --
+    or None when there is none or the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", profile)
     try:
         kv = {}
         with open(path) as f:
@@ -58,7 +69,7 @@ def _traffic_bytes():
                 if line.strip() and not line.startswith("#"):
                     k, v = line.split()
                     kv[k] = v
-        if kv.get("source_hash") != _kernel_source_hash():
+        if kv.get("source_hash") != _kernel_source_hash(sources):
             return None
         return (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
                 float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
@@ -143,49 +154,63 @@ def main(argv=None):
     def step(prec):
         return lambda: rq.price_caplets(model, N, M, seed, precision=prec, device=dev, ws=ws)
 
+    # 1) the full hot path: FP32 prices + 161 Greeks (adjoint kernel)
+    wsg = torch.empty(rq.caplets_workspace(model, N, M, 0, "fp32", greeks=True), dtype=torch.uint8, device=dev)
+    ms_g, kms_g, res_g = _time_steps(
+        lambda: rq.price_caplets(model, N, M, seed, precision="fp32", greeks=True, device=dev, ws=wsg),
+        args.steps, args.warmup)
+    # 2) prices only, FP32 and the plain FP64 form, same points
     head = args.precision
     ms, kms, res = _time_steps(step(head), args.steps, args.warmup)
-    se_head = res.se[-1].item()
-    rq_head = res.mean[-1].item()
     out_extra = {}
     if not args.skip_fp64 and head != "fp64":
         ms64, kms64, res64 = _time_steps(step("fp64"), args.steps, args.warmup)
-        se64 = res64.se[-1].item()
+        rq64, se64 = res64.mean[-1].item(), res64.se[-1].item()
         out_extra = {
             "fp64_paths_per_s": N * M / (ms64 / 1e3),
             "fp64_ms_per_step": ms64,
             "fp64_kernel_ms": kms64,
-            "speedup_vs_fp64": ms64 / ms,
-            "book_rq": {"fp32": rq_head, "fp64": res64.mean[-1].item()},
-            "book_se": {"fp32": se_head, "fp64": se64},
-            "se_ratio": se_head / se64,
-            "book_rel_diff_fp32_vs_fp64": abs(rq_head - res64.mean[-1].item()) / abs(res64.mean[-1].item()),
+            "speedup_vs_fp64": ms64 / ms_g,
+            "book_rq": {"fp32_greeks": res_g.mean[-1].item(), "fp32": res.mean[-1].item(), "fp64": rq64},
+            "book_se": {"fp32_greeks": res_g.se[-1].item(), "fp32": res.se[-1].item(), "fp64": se64},
+            "se_ratio": res_g.se[-1].item() / se64,
+            "book_rel_diff_fp32_vs_fp64": abs(res_g.mean[-1].item() - rq64) / abs(rq64),
         }
+    gm, gse = res_g.greeks.mean, res_g.greeks.se
+    out_extra["greeks"] = {
+        "n": N_GREEKS_LMM80,
+        "delta_L40": gm[39].item(), "delta_L40_se": gse[39].item(),
+        "vega_s40": gm[81 + 39].item(), "vega_s40_se": gse[81 + 39].item(),
+        "delta_spot": gm[80].item(),
+    }
+    out_extra["prices_only_fp32"] = {
+        "paths_per_s": N * M / (ms / 1e3), "ms_per_step": ms, "kernel_ms": kms,
+        "achieved_tflops": FLOPS_PER_PATH_LMM80 * N * M / (kms / 1e3) / 1e12,
+        "traffic": _traffic_bytes("lmm80_3f_fp32_traffic.txt", PRICE_SOURCES)}
 
-    dtype = "f32" if head == "fp32" else "f64"
-    achieved = FLOPS_PER_PATH_LMM80 * N * M / (kms / 1e3) / 1e12
+    dtype = "f32"
+    achieved = FLOPS_PER_PATH_LMM80_GREEKS * N * M / (kms_g / 1e3) / 1e12
     peak = PEAK_TFLOPS[dtype]
     line = {
         "metric": "RQMC paths/s + Greeks/s (LMM 80-fwd caplets) vs plain FP64, at equal std err",
-        "value": N * M / (ms / 1e3),
+        "value": N * M / (ms_g / 1e3),
         "unit": "paths/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": ms_g,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": "lmm80_3f_caplet_book", "n_fwd": 80, "n_factors": 3, "s": 240,
-                   "N": N, "M": M, "seed": seed, "precision": head, "greeks": False},
-        "greeks_per_s": None,
+        "config": {"workload": "lmm80_3f_caplet_book_greeks", "n_fwd": 80, "n_factors": 3, "s": 240,
+                   "N": N, "M": M, "seed": seed, "precision": "fp32", "greeks": N_GREEKS_LMM80},
+        "greeks_per_s": N * M * N_GREEKS_LMM80 / (ms_g / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": _traffic_bytes() if dtype == "f32" else None,
-                     "kernel": "lmm_kernel<80,3,%s>" % ("float" if dtype == "f32" else "double"),
-                     "kernel_ms": kms},
+                     "traffic": _traffic_bytes("lmm80_3f_fp32_greeks_traffic.txt", ADJ_SOURCES),
+                     "kernel": "lmm_adjoint_kernel<80,3,float>", "kernel_ms": kms_g},
     }
     line.update(out_extra)
     if not args.no_cpu_baseline:

@@ -139,9 +139,9 @@ typedef struct {
  * Return 0 when the arguments would be rejected (rq_last_error says why). */
 size_t rq_sequence_workspace(int s, int64_t N, int M, int flags);
 size_t rq_caplets_workspace(const rq_lmm_model *model, int64_t N, int M, int flags,
-                            rq_precision prec);
+                            rq_precision prec, int with_greeks);
 size_t rq_mbs_workspace(const rq_mbs_params *params, int64_t N, int M, int flags,
-                        rq_precision prec);
+                        rq_precision prec, int with_greeks);
 
 /* sequence(s, N, M, seed): the points themselves (Algorithm 3 for every
  * base, all replications in one launch).
@@ -154,22 +154,37 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
 
 /* price_caplets(model, N, M): caplets and book of the LIBOR market model.
  *   out       results with n_out = n_fwd + 1
+ *   grad      NULL, or pathwise Greeks of the book from the adjoint kernel,
+ *             n_g = 2 n_fwd + 1 outputs per replication: [0, n_fwd)
+ *             dbook/dL_n(0) for n = 1..n_fwd (strikes held fixed); [n_fwd]
+ *             dbook/dL_0(0) (the spot rate, through the numeraire);
+ *             [n_fwd + 1, 2 n_fwd + 1) dbook/dsigma_n for n = 1..n_fwd.
+ *             theta holds the per-replication estimates, mean/sd/se their
+ *             grand average and spread (as for prices).
  *   per_path  optional device [M][N][n_out] FP64: every path's discounted
  *             payoffs (a verification hook; NULL in production)
  *   prec      RQ_FP64: all path arithmetic in FP64.  RQ_FP32: forwards,
  *             drifts and normals in FP32; digits, points, numeraire,
- *             payoffs and all reductions stay FP64. */
+ *             payoffs and all reductions stay FP64.
+ * With grad != NULL the prices come from the adjoint kernel's forward pass
+ * (same scheme; it keeps its state in log2 units, so FP64 prices agree
+ * with the pricing kernel's to rounding). */
 rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t seed,
                            int64_t m_offset, int flags, rq_precision prec,
-                           const rq_result *out, double *per_path, void *ws, size_t ws_bytes,
-                           void *stream);
+                           const rq_result *out, const rq_result *grad, double *per_path,
+                           void *ws, size_t ws_bytes, void *stream);
 
 /* price_mbs(params, N, M): present value of the mortgage pool.
+ *   grad  NULL, or the pathwise total derivative dPV/di0 (one output per
+ *         replication; rates scale with i0 and the payment c and the
+ *         annuity factors c_k move with it), carried forward along each
+ *         path as a tangent.
  *   prec  RQ_FP32 keeps the rate, prepayment and pool fraction in FP32 and
  *         the discount factor, cash-flow products and reductions in FP64. */
 rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t seed,
                        int64_t m_offset, int flags, rq_precision prec, const rq_result *out,
-                       double *per_path, void *ws, size_t ws_bytes, void *stream);
+                       const rq_result *grad, double *per_path, void *ws, size_t ws_bytes,
+                       void *stream);
 
 /* inv_normal: the inverse standard normal CDF used on every path
  * dimension, applied elementwise (a verification and utility entry).

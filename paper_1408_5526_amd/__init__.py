@@ -72,20 +72,20 @@ def lib():
     L.rq_sequence_workspace.restype = C.c_size_t
     L.rq_sequence_workspace.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int]
     L.rq_caplets_workspace.restype = C.c_size_t
-    L.rq_caplets_workspace.argtypes = [C.POINTER(rq_lmm_model), C.c_int64, C.c_int, C.c_int, C.c_int]
+    L.rq_caplets_workspace.argtypes = [C.POINTER(rq_lmm_model), C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int]
     L.rq_mbs_workspace.restype = C.c_size_t
-    L.rq_mbs_workspace.argtypes = [C.POINTER(rq_mbs_params), C.c_int64, C.c_int, C.c_int, C.c_int]
+    L.rq_mbs_workspace.argtypes = [C.POINTER(rq_mbs_params), C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int]
     L.rq_sequence.restype = C.c_int
     L.rq_sequence.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_uint64, C.c_int, C.c_int64,
                               C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     L.rq_price_caplets.restype = C.c_int
     L.rq_price_caplets.argtypes = [C.POINTER(rq_lmm_model), C.c_int64, C.c_int, C.c_uint64, C.c_int64,
-                                   C.c_int, C.c_int, C.POINTER(rq_result), C.c_void_p, C.c_void_p,
-                                   C.c_size_t, C.c_void_p]
+                                   C.c_int, C.c_int, C.POINTER(rq_result), C.POINTER(rq_result),
+                                   C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     L.rq_price_mbs.restype = C.c_int
     L.rq_price_mbs.argtypes = [C.POINTER(rq_mbs_params), C.c_int64, C.c_int, C.c_uint64, C.c_int64,
-                               C.c_int, C.c_int, C.POINTER(rq_result), C.c_void_p, C.c_void_p,
-                               C.c_size_t, C.c_void_p]
+                               C.c_int, C.c_int, C.POINTER(rq_result), C.POINTER(rq_result),
+                               C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     L.rq_inv_normal.restype = C.c_int
     L.rq_inv_normal.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     L.rq_timer_begin.restype = C.c_int
@@ -148,12 +148,14 @@ def _mbs_c(p) -> rq_mbs_params:
 @dataclass
 class Result:
     """Per-replication estimates theta [M][n_out], RQ, sd (M-1), SE, all FP64
-    device tensors; per_path [M][N][n_out] when requested."""
+    device tensors; per_path [M][N][n_out] when requested; greeks (another
+    Result) when requested."""
     theta: object
     mean: object
     sd: object
     se: object
     per_path: Optional[object] = None
+    greeks: Optional["Result"] = None
 
 
 def _result(M: int, n_out: int, device):
@@ -201,64 +203,145 @@ def sequence(s: int, N: int, M: int, seed: int, flags: int = 0, m_offset: int = 
     return out
 
 
-def caplets_workspace(model, N: int, M: int, flags: int = 0, precision="fp64") -> int:
+def caplets_workspace(model, N: int, M: int, flags: int = 0, precision="fp64",
+                      greeks: bool = False) -> int:
     h = _LmmHost(model)
-    n = lib().rq_caplets_workspace(C.byref(h.c), N, M, flags, _prec(precision))
+    n = lib().rq_caplets_workspace(C.byref(h.c), N, M, flags, _prec(precision), int(greeks))
     if n == 0:
         raise RqError(RQ_EINVAL, last_error())
     return n
 
 
 def price_caplets(model, N: int, M: int, seed: int, m_offset: int = 0, flags: int = 0,
-                  precision="fp64", per_path: bool = False, device=None, ws=None) -> Result:
+                  precision="fp64", per_path: bool = False, greeks: bool = False,
+                  device=None, ws=None) -> Result:
     """Caplets on every forward with a strike, plus the book (last output),
-    n_out = n_fwd + 1."""
+    n_out = n_fwd + 1.  greeks=True runs the adjoint kernel and adds
+    result.greeks with 2 n_fwd + 1 outputs: dbook/dL_n(0) (n = 1..n_fwd),
+    dbook/dL_0(0), dbook/dsigma_n (n = 1..n_fwd)."""
     torch = _torch()
     dev = _device(device)
     h = _LmmHost(model)
     prec = _prec(precision)
     n_out = model.n_fwd + 1
     res, c = _result(M, n_out, dev)
+    gres, gc = _result(M, 2 * model.n_fwd + 1, dev) if greeks else (None, None)
     pp = torch.empty((M, N, n_out), dtype=torch.float64, device=dev) if per_path else None
-    need = lib().rq_caplets_workspace(C.byref(h.c), N, M, flags, prec)
+    need = lib().rq_caplets_workspace(C.byref(h.c), N, M, flags, prec, int(greeks))
     if need == 0:
         raise RqError(RQ_EINVAL, last_error())
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)
     _check(lib().rq_price_caplets(C.byref(h.c), N, M, seed, m_offset, flags, prec, C.byref(c),
+                                  C.byref(gc) if greeks else None,
                                   C.c_void_p(pp.data_ptr() if pp is not None else 0),
                                   C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)))
     res.per_path = pp
+    res.greeks = gres
     return res
 
 
-def mbs_workspace(params, N: int, M: int, flags: int = 0, precision="fp64") -> int:
+def mbs_workspace(params, N: int, M: int, flags: int = 0, precision="fp64", greeks: bool = False) -> int:
     p = _mbs_c(params)
-    n = lib().rq_mbs_workspace(C.byref(p), N, M, flags, _prec(precision))
+    n = lib().rq_mbs_workspace(C.byref(p), N, M, flags, _prec(precision), int(greeks))
     if n == 0:
         raise RqError(RQ_EINVAL, last_error())
     return n
 
 
 def price_mbs(params, N: int, M: int, seed: int, m_offset: int = 0, flags: int = 0,
-              precision="fp64", per_path: bool = False, device=None, ws=None) -> Result:
-    """Present value of the MBS pool, n_out = 1."""
+              precision="fp64", per_path: bool = False, greeks: bool = False,
+              device=None, ws=None) -> Result:
+    """Present value of the MBS pool, n_out = 1; greeks=True adds the
+    pathwise total derivative dPV/di0 as result.greeks."""
     torch = _torch()
     dev = _device(device)
     p = _mbs_c(params)
     prec = _prec(precision)
     res, c = _result(M, 1, dev)
+    gres, gc = _result(M, 1, dev) if greeks else (None, None)
     pp = torch.empty((M, N, 1), dtype=torch.float64, device=dev) if per_path else None
-    need = lib().rq_mbs_workspace(C.byref(p), N, M, flags, prec)
+    need = lib().rq_mbs_workspace(C.byref(p), N, M, flags, prec, int(greeks))
     if need == 0:
         raise RqError(RQ_EINVAL, last_error())
     if ws is None or ws.numel() < need:
         ws = _workspace(need, dev)
     _check(lib().rq_price_mbs(C.byref(p), N, M, seed, m_offset, flags, prec, C.byref(c),
+                              C.byref(gc) if greeks else None,
                               C.c_void_p(pp.data_ptr() if pp is not None else 0),
                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)))
     res.per_path = pp
+    res.greeks = gres
     return res
+
+
+# ---------------------------------------------------------------------------
+# autograd wrappers: the Greeks come from the adjoint kernel (LIBOR) and the
+# pathwise tangent (MBS); backward only scales them by the incoming gradient
+# ---------------------------------------------------------------------------
+def _autograd():
+    import torch
+
+    class CapletBook(torch.autograd.Function):
+        """RQ_{M,N} of the caplet book as a function of the initial forward
+        curve L0 [n_fwd+1] and the vols sigma [n_fwd+1] (CPU float64
+        tensors); backward returns g * dRQ/dL0 and g * dRQ/dsigma from the
+        adjoint kernel.  The per-replication Greek estimates and their SE are
+        kept in ctx.greeks (a Result) and returned by CapletBook.last."""
+
+        last = None
+
+        @staticmethod
+        def forward(ctx, L0, sigma, model, N, M, seed, precision="fp32", device=None):
+            m = model.copy()
+            m.L0 = L0.detach().cpu().double().numpy().copy()
+            m.sigma = sigma.detach().cpu().double().numpy().copy()
+            r = price_caplets(m, N, M, seed, precision=precision, greeks=True, device=device)
+            gm = r.greeks.mean.cpu()
+            nf = m.n_fwd
+            dL0 = torch.zeros(nf + 1, dtype=torch.float64)
+            dL0[0] = gm[nf]
+            dL0[1:] = gm[:nf]
+            dsig = torch.zeros(nf + 1, dtype=torch.float64)
+            dsig[1:] = gm[nf + 1:]
+            ctx.save_for_backward(dL0, dsig)
+            CapletBook.last = r
+            return r.mean[-1].detach().cpu().reshape(())
+
+        @staticmethod
+        def backward(ctx, g):
+            dL0, dsig = ctx.saved_tensors
+            return g * dL0, g * dsig, None, None, None, None, None, None
+
+    class MBSPrice(torch.autograd.Function):
+        """RQ_{M,N} of the MBS as a function of i0 (0-dim CPU float64
+        tensor); backward returns g * dRQ/di0 from the pathwise tangent."""
+
+        last = None
+
+        @staticmethod
+        def forward(ctx, i0, params, N, M, seed, precision="fp32", device=None):
+            from dataclasses import replace
+            p = replace(params, i0=float(i0.detach().cpu()))
+            r = price_mbs(p, N, M, seed, precision=precision, greeks=True, device=device)
+            ctx.save_for_backward(r.greeks.mean.cpu().reshape(()))
+            MBSPrice.last = r
+            return r.mean[0].detach().cpu().reshape(())
+
+        @staticmethod
+        def backward(ctx, g):
+            (d,) = ctx.saved_tensors
+            return g * d, None, None, None, None, None, None
+
+    return CapletBook, MBSPrice
+
+
+def __getattr__(name):
+    if name in ("CapletBook", "MBSPrice"):
+        cb, mp = _autograd()
+        globals()["CapletBook"], globals()["MBSPrice"] = cb, mp
+        return globals()[name]
+    raise AttributeError(name)
 
 
 def inv_normal(u, precision="fp64"):

@@ -385,6 +385,38 @@ std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
 }
 
 int lmm_blocks(int64_t N) { return (int)((N + rq::kBlock - 1) / rq::kBlock); }
+int adj_blocks(int64_t N) { return (int)((N + rq::kAdjBlockHost - 1) / rq::kAdjBlockHost); }
+
+// Adjoint table (layout in rq_internal.h) in the kernel's precision.
+template <typename T>
+std::vector<uint8_t> adj_table(const rq_lmm_model *m)
+{
+    const int nf = m->n_fwd, d = m->n_factors;
+    const double log2e = 1.4426950408889634074;
+    std::vector<T> t((size_t)lmm_rows(nf) * rq::kAdjRow, T(0));
+    for (int n = 1; n <= nf; ++n) {
+        T *r = &t[(size_t)(n - 1) * rq::kAdjRow];
+        const double sg = m->sigma[n];
+        double b2 = 0.0, a2 = 0.0;
+        for (int f = 0; f < d; ++f) {
+            const double b = m->loadings[(size_t)(n - 1) * d + f];
+            const double a = sg * b;
+            r[f] = (T)(log2e * a);
+            r[3 + f] = (T)(m->delta * a);
+            r[9 + f] = (T)(log2e * b);
+            r[12 + f] = (T)(m->delta * b);
+            b2 += b * b;
+            a2 += a * a;
+        }
+        r[6] = (T)(log2e * (-0.5 * a2 * m->delta));
+        r[7] = (T)std::log2(m->delta * m->L0[n]);
+        r[8] = (T)(log2e * m->delta * a2);
+        r[15] = (T)(log2e * m->delta * sg * b2);
+    }
+    std::vector<uint8_t> out(t.size() * sizeof(T));
+    std::memcpy(out.data(), t.data(), out.size());
+    return out;
+}
 
 // ---- MBS model ---------------------------------------------------------------
 
@@ -400,22 +432,29 @@ rq_status check_mbs(const rq_mbs_params *p)
     return RQ_OK;
 }
 
-// c_k = sum_{j=0}^{K-k} (1+i0)^{-j} for k = 0..K (geometric series).
+// c_k = sum_{j=0}^{K-k} (1+i0)^{-j} for k = 0..K (geometric series), then
+// dc_k/di0 = sum_{j=1}^{K-k} -j (1+i0)^{-j-1}.
 std::vector<uint8_t> mbs_table(const rq_mbs_params *p)
 {
     const int K = p->months;
-    std::vector<double> ck(K + 1, 0.0);
+    std::vector<double> ck(2 * (size_t)(K + 1), 0.0);
     const double v = 1.0 / (1.0 + p->i0);
-    // accumulate from the end: c_K = 1, c_k = 1 + v c_{k+1}
+    // accumulate from the end: c_K = 1, c_k = 1 + v c_{k+1};
+    // dc_K = 0, dc_k = v (dc_{k+1} - v c_{k+1})  (since dv/di0 = -v^2)
     ck[K] = 1.0;
-    for (int k = K - 1; k >= 1; --k) ck[k] = 1.0 + v * ck[k + 1];
+    double *dck = ck.data() + (K + 1);
+    dck[K] = 0.0;
+    for (int k = K - 1; k >= 1; --k) {
+        ck[k] = 1.0 + v * ck[k + 1];
+        dck[k] = v * dck[k + 1] - v * v * ck[k + 1];
+    }
     std::vector<uint8_t> out(ck.size() * sizeof(double));
     std::memcpy(out.data(), ck.data(), out.size());
     return out;
 }
 
-rq_status finish(const rq_result *out, double *partial, int M, int n_blk, int n_out, int64_t N,
-                 hipStream_t st)
+rq_status finish(const rq_result *out, const double *partial, int stride, int off, int M, int n_blk,
+                 int n_out, int64_t N, hipStream_t st)
 {
     rq::ReduceArgs r;
     r.partial = partial;
@@ -423,6 +462,8 @@ rq_status finish(const rq_result *out, double *partial, int M, int n_blk, int n_
     r.M = M;
     r.n_blk = n_blk;
     r.n_out = n_out;
+    r.stride = stride;
+    r.off = off;
     r.Nd = (double)N;
     RQ_HIP(rq::launch_reduce(r, st));
     if (out->mean || out->sd || out->se) {
@@ -526,35 +567,66 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
     return RQ_OK;
 }
 
-size_t rq_caplets_workspace(const rq_lmm_model *model, int64_t N, int M, int flags, rq_precision prec)
+// Model-region bytes and partial-region bytes of a LIBOR call.
+static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greeks, size_t &mb, size_t &pb,
+                         int &n_blk)
+{
+    const int rows = lmm_rows(model->n_fwd);
+    const int n_out = model->n_fwd + 1;
+    const int n_g = 2 * model->n_fwd + 1;
+    mb = (size_t)rows * (rq::kFwdRow * sizeof(double) + rq::kRow32 * sizeof(float));
+    if (greeks) {
+        mb += (size_t)rows * rq::kAdjRow * sizeof(double);   // room for either precision
+        n_blk = adj_blocks(N);
+        pb = (size_t)M * n_blk * (n_out + n_g) * sizeof(double);
+    } else {
+        n_blk = lmm_blocks(N);
+        pb = (size_t)M * n_blk * n_out * sizeof(double);
+    }
+}
+
+size_t rq_caplets_workspace(const rq_lmm_model *model, int64_t N, int M, int flags, rq_precision prec,
+                            int with_greeks)
 {
     if (check_lmm(model) != RQ_OK) return 0;
     Geometry g;
     const int s = model->n_fwd * model->n_factors;
     if (check_common(s, N, M, flags, 0, g) != RQ_OK) return 0;
     (void)prec;
-    const size_t mb = (size_t)lmm_rows(model->n_fwd) * (rq::kFwdRow * sizeof(double) + rq::kRow32 * sizeof(float));
-    const size_t pb = (size_t)M * lmm_blocks(N) * (model->n_fwd + 1) * sizeof(double);
+    size_t mb, pb;
+    int n_blk;
+    caplet_sizes(model, N, M, with_greeks != 0, mb, pb, n_blk);
     return layout(s, g, M, flags, mb, pb).total;
 }
 
 rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t seed, int64_t m_offset,
-                           int flags, rq_precision prec, const rq_result *out, double *per_path,
-                           void *ws, size_t ws_bytes, void *stream)
+                           int flags, rq_precision prec, const rq_result *out, const rq_result *grad,
+                           double *per_path, void *ws, size_t ws_bytes, void *stream)
 {
     rq_status stt = check_lmm(model);
     if (stt) return stt;
     if (flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "RQ_OUT_DIGITS applies to rq_sequence only");
     if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
     if (!out || !out->theta) return fail(RQ_EINVAL, "out->theta is NULL");
+    if (grad && !grad->theta) return fail(RQ_EINVAL, "grad->theta is NULL");
     const int s = model->n_fwd * model->n_factors;
     Geometry g;
     if ((stt = check_common(s, N, M, flags, m_offset, g))) return stt;
-    const int n_blk = lmm_blocks(N);
+    const bool greeks = grad != nullptr;
+    size_t mb, pb;
+    int n_blk;
+    caplet_sizes(model, N, M, greeks, mb, pb, n_blk);
     const int n_out = model->n_fwd + 1;
+    const int n_g = 2 * model->n_fwd + 1;
     if ((int64_t)n_blk * M >= (1ll << 31)) return fail(RQ_ERANGE, "N*M too large for one launch");
     std::vector<uint8_t> tab = lmm_table(model);
-    const Layout L = layout(s, g, M, flags, tab.size(), (size_t)M * n_blk * n_out * sizeof(double));
+    const size_t adj_off = tab.size();
+    if (greeks) {
+        std::vector<uint8_t> at = prec == RQ_FP32 ? adj_table<float>(model) : adj_table<double>(model);
+        tab.insert(tab.end(), at.begin(), at.end());
+    }
+    tab.resize(mb, 0);
+    const Layout L = layout(s, g, M, flags, mb, pb);
     if ((stt = check_ws(ws, ws_bytes, L.total))) return stt;
     PointTables pt;
     if ((stt = build_point_tables(s, g, seed, flags, pt))) return stt;
@@ -565,7 +637,10 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     a.g = seq_geom(L, g, w, s, M, N, flags);
     a.fwd = reinterpret_cast<const double *>(w + L.model);
     a.fwd32 = reinterpret_cast<const float *>(w + L.model + (size_t)lmm_rows(model->n_fwd) * rq::kFwdRow * sizeof(double));
+    a.adj = greeks ? (const void *)(w + L.model + adj_off) : nullptr;
     a.partial = reinterpret_cast<double *>(w + L.partial);
+    a.partial_g = greeks ? a.partial + (size_t)M * n_blk * n_out : nullptr;
+    a.n_g = n_g;
     a.per_path = per_path;
     a.n_fwd = model->n_fwd;
     a.n_out = n_out;
@@ -575,38 +650,44 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     a.num0 = 1.0 + model->delta * model->L0[0];
     {
         TimedRegion tr(st);
-        RQ_HIP(rq::launch_lmm(a, model->n_factors, prec == RQ_FP32, st));
+        if (greeks) RQ_HIP(rq::launch_lmm_adjoint(a, model->n_factors, prec == RQ_FP32, st));
+        else RQ_HIP(rq::launch_lmm(a, model->n_factors, prec == RQ_FP32, st));
     }
-    return finish(out, a.partial, M, n_blk, n_out, N, st);
+    if ((stt = finish(out, a.partial, n_out, 0, M, n_blk, n_out, N, st))) return stt;
+    if (greeks) return finish(grad, a.partial_g, n_g, 0, M, n_blk, n_g, N, st);
+    return RQ_OK;
 }
 
-size_t rq_mbs_workspace(const rq_mbs_params *params, int64_t N, int M, int flags, rq_precision prec)
+size_t rq_mbs_workspace(const rq_mbs_params *params, int64_t N, int M, int flags, rq_precision prec,
+                        int with_greeks)
 {
     if (check_mbs(params) != RQ_OK) return 0;
     Geometry g;
     if (check_common(params->months, N, M, flags, 0, g) != RQ_OK) return 0;
     (void)prec;
-    const size_t mb = (size_t)(params->months + 1) * sizeof(double);
-    const size_t pb = (size_t)M * lmm_blocks(N) * sizeof(double);
+    const size_t mb = 2 * (size_t)(params->months + 1) * sizeof(double);
+    const size_t pb = (size_t)M * lmm_blocks(N) * (with_greeks ? 2 : 1) * sizeof(double);
     return layout(params->months, g, M, flags, mb, pb).total;
 }
 
 rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t seed, int64_t m_offset,
-                       int flags, rq_precision prec, const rq_result *out, double *per_path, void *ws,
-                       size_t ws_bytes, void *stream)
+                       int flags, rq_precision prec, const rq_result *out, const rq_result *grad,
+                       double *per_path, void *ws, size_t ws_bytes, void *stream)
 {
     rq_status stt = check_mbs(params);
     if (stt) return stt;
     if (flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "RQ_OUT_DIGITS applies to rq_sequence only");
     if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
     if (!out || !out->theta) return fail(RQ_EINVAL, "out->theta is NULL");
+    if (grad && !grad->theta) return fail(RQ_EINVAL, "grad->theta is NULL");
     const int s = params->months;
     Geometry g;
     if ((stt = check_common(s, N, M, flags, m_offset, g))) return stt;
     const int n_blk = lmm_blocks(N);
+    const int n_part = grad ? 2 : 1;
     if ((int64_t)n_blk * M >= (1ll << 31)) return fail(RQ_ERANGE, "N*M too large for one launch");
     std::vector<uint8_t> tab = mbs_table(params);
-    const Layout L = layout(s, g, M, flags, tab.size(), (size_t)M * n_blk * sizeof(double));
+    const Layout L = layout(s, g, M, flags, tab.size(), (size_t)M * n_blk * n_part * sizeof(double));
     if ((stt = check_ws(ws, ws_bytes, L.total))) return stt;
     PointTables pt;
     if ((stt = build_point_tables(s, g, seed, flags, pt))) return stt;
@@ -620,6 +701,7 @@ rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t s
     a.per_path = per_path;
     a.months = params->months;
     a.n_blk = n_blk;
+    a.n_part = n_part;
     a.i0 = params->i0;
     a.sig = params->sigma;
     a.K0 = std::exp(-0.5 * params->sigma * params->sigma);
@@ -627,12 +709,18 @@ rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t s
     a.K2 = params->K2;
     a.K3 = params->K3;
     a.K4 = params->K4;
-    a.c = params->i0 / (1.0 - std::pow(1.0 + params->i0, -(double)params->months));
+    const double vK = std::pow(1.0 + params->i0, -(double)params->months);
+    a.c = params->i0 / (1.0 - vK);
+    // dc/di0 with dv/di0 = -K (1+i0)^{-K-1}
+    const double dvK = -params->months * vK / (1.0 + params->i0);
+    a.dc = ((1.0 - vK) + params->i0 * dvK) / ((1.0 - vK) * (1.0 - vK));
     {
         TimedRegion tr(st);
         RQ_HIP(rq::launch_mbs(a, prec == RQ_FP32, st));
     }
-    return finish(out, a.partial, M, n_blk, 1, N, st);
+    if ((stt = finish(out, a.partial, n_part, 0, M, n_blk, 1, N, st))) return stt;
+    if (grad) return finish(grad, a.partial, n_part, 1, M, n_blk, 1, N, st);
+    return RQ_OK;
 }
 
 }  // extern "C"

@@ -281,6 +281,18 @@ struct Acc {
     double s, c;
 };
 
+// Read-only parameter tables are read through the constant address space:
+// the kernel never writes them, so the compiler may use scalar loads even
+// after the kernel has stored to global memory.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const void *p)
+{
+    return (cptr<T>)p;
+}
+
 __device__ __forceinline__ void acc_add(Acc &a, double x)
 {
     const double t = a.s + x;

@@ -94,10 +94,20 @@ constexpr int kFwdRow = 12;
 constexpr int kRow32 = 8;
 constexpr int kGrp = 4;   // forwards per branch-free group of the LIBOR kernel
 
+// Adjoint table, kAdjRow entries per forward in the kernel's precision:
+//   [0..2] log2(e) a_n     [3..5] delta a_n     [6] log2(e) c_n
+//   [7]    log2(delta L_n(0))                    [8] q_n = log2(e) delta |a_n|^2
+//   [9..11] log2(e) b_n    [12..14] delta b_n   [15] log2(e) delta sigma_n |b_n|^2
+// where b_n = a_n / sigma_n is the unit loading row.
+constexpr int kAdjRow = 16;
+
 struct LmmArgs {
     SeqGeom g;
     const double *fwd;       // [n_fwd][kFwdRow]
     const float *fwd32;      // [n_fwd][kRow32]
+    const void *adj;         // [n_fwd][kAdjRow] (FP32 or FP64) or nullptr
+    double *partial_g;       // [M][n_blk][n_g] Greek partial sums or nullptr
+    int n_g;                 // 2 n_fwd + 1
     double *partial;         // [M][n_blk][n_out]
     double *per_path;        // [M][N][n_out] or nullptr
     int n_fwd;
@@ -108,18 +118,20 @@ struct LmmArgs {
 
 struct MbsArgs {
     SeqGeom g;
-    const double *ck;        // [months+1]: c_k
-    double *partial;         // [M][n_blk][1]
+    const double *ck;        // [months+1]: c_k, then [months+1]: dc_k/di0
+    double *partial;         // [M][n_blk][n_part] (PV, then dPV/di0 with Greeks)
     double *per_path;        // [M][N] or nullptr
     int months;
     int n_blk;
-    double i0, sig, K0, K1, K2, K3, K4, c;
+    int n_part;              // 1, or 2 with the tangent
+    double i0, sig, K0, K1, K2, K3, K4, c, dc;   // dc = dc/di0
 };
 
 struct ReduceArgs {
-    const double *partial;   // [M][n_blk][n_out]
+    const double *partial;   // [M][n_blk][stride], outputs at [off, off + n_out)
     double *theta;           // [M][n_out]
     int M, n_blk, n_out;
+    int stride, off;
     double Nd;               // N as FP64
 };
 
@@ -133,7 +145,9 @@ struct FinalizeArgs {
 hipError_t launch_setup(const SetupArgs &a, hipStream_t st);
 hipError_t launch_sequence(const SeqGeom &g, int flags, void *out, hipStream_t st);
 hipError_t launch_lmm(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
-hipError_t launch_mbs(const MbsArgs &a, int fp32, hipStream_t st);
+hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
+constexpr int kAdjBlockHost = 128;   // threads per block of the adjoint kernel
+hipError_t launch_mbs(const MbsArgs &a, int fp32, hipStream_t st);   // n_part == 2: tangent
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);
 hipError_t launch_inv_normal(int64_t n, const double *u, void *z, int fp32, hipStream_t st);

@@ -1,0 +1,11 @@
+// rq_lmm_adj32.hip -- FP32 instantiations of the LIBOR adjoint kernel.
+#include "rq_lmm_adj.h"
+
+namespace rq {
+
+hipError_t launch_lmm_adjoint_f32(const LmmArgs &a, int n_factors, hipStream_t st)
+{
+    return launch_adj_prec<float>(a, n_factors, st);
+}
+
+}  // namespace rq

@@ -1,0 +1,17 @@
+// rq_lmm_adj64.hip -- FP64 instantiations of the LIBOR adjoint kernel and the
+// precision dispatch.
+#include "rq_lmm_adj.h"
+
+namespace rq {
+
+hipError_t launch_lmm_adjoint_f64(const LmmArgs &a, int n_factors, hipStream_t st)
+{
+    return launch_adj_prec<double>(a, n_factors, st);
+}
+
+hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, hipStream_t st)
+{
+    return fp32 ? launch_lmm_adjoint_f32(a, n_factors, st) : launch_lmm_adjoint_f64(a, n_factors, st);
+}
+
+}  // namespace rq

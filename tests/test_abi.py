@@ -45,7 +45,7 @@ def test_workspace_sizes_and_validation():
 def _call_caplets(model, N=256, M=2, ws_bytes=1 << 20, flags=0, prec=0, theta=1):
     h = rq._LmmHost(model)
     res = rq.rq_result(theta, 0, 0, 0)
-    return rq.lib().rq_price_caplets(C.byref(h.c), N, M, 1, 0, flags, prec, C.byref(res), None,
+    return rq.lib().rq_price_caplets(C.byref(h.c), N, M, 1, 0, flags, prec, C.byref(res), None, None,
                                      C.c_void_p(256), ws_bytes, None)
 
 
@@ -68,16 +68,24 @@ def test_caplet_argument_errors_return_before_launch():
     assert _call_caplets(m, flags=rq.OUT_DIGITS) == rq.RQ_EINVAL
     assert _call_caplets(m, prec=7) == rq.RQ_EINVAL
     assert _call_caplets(m, ws_bytes=16) == rq.RQ_EWORKSPACE and "needed" in rq.last_error()
+    # the Greeks need a larger workspace than the prices alone
+    h = rq._LmmHost(m)
+    assert rq.lib().rq_caplets_workspace(C.byref(h.c), 4096, 4, 0, 1, 1) > \
+        rq.lib().rq_caplets_workspace(C.byref(h.c), 4096, 4, 0, 1, 0)
 
 
 def test_mbs_argument_errors_return_before_launch():
     p = rq._mbs_c(I.MbsParams(0, 0.007, 0.02, 0.01, -0.005, 10, 0.5))
     res = rq.rq_result(1, 0, 0, 0)
-    st = rq.lib().rq_price_mbs(C.byref(p), 64, 1, 1, 0, 0, 0, C.byref(res), None, C.c_void_p(256), 1 << 20, None)
+    st = rq.lib().rq_price_mbs(C.byref(p), 64, 1, 1, 0, 0, 0, C.byref(res), None, None, C.c_void_p(256), 1 << 20, None)
     assert st == rq.RQ_EINVAL and "months" in rq.last_error()
     p = rq._mbs_c(I.MbsParams(12, 0.007, -0.02, 0.01, -0.005, 10, 0.5))
-    st = rq.lib().rq_price_mbs(C.byref(p), 64, 1, 1, 0, 0, 0, C.byref(res), None, C.c_void_p(256), 1 << 20, None)
+    st = rq.lib().rq_price_mbs(C.byref(p), 64, 1, 1, 0, 0, 0, C.byref(res), None, None, C.c_void_p(256), 1 << 20, None)
     assert st == rq.RQ_EINVAL
+    bad = rq.rq_result(0, 0, 0, 0)
+    p = rq._mbs_c(I.mbs_paper(12))
+    st = rq.lib().rq_price_mbs(C.byref(p), 64, 1, 1, 0, 0, 0, C.byref(res), C.byref(bad), None, C.c_void_p(256), 1 << 20, None)
+    assert st == rq.RQ_EINVAL and "grad" in rq.last_error()
 
 
 def test_misaligned_workspace_rejected():
