@@ -34,12 +34,12 @@ if ROOT not in sys.path:
 # add/mul = 1, each special function = 1): 3,240 forward-steps x 26, 240
 # inverse normals x 32, 80 payoffs x 12, 240 point divisions.
 FLOPS_PER_PATH_LMM80 = 93_040
-# Price + 161 Greeks per path: the forward pass above, the adjoint of each of
-# the 3,240 forward-steps (42 flops: the suffix sum of the w adjoint, the
-# drift-factor adjoint and its derivative, the vega terms, rewinding w), the
-# 240 normals regenerated for the reverse sweep (33 each) and the adjoint of
-# the 80 payoffs (20 each).
-FLOPS_PER_PATH_LMM80_GREEKS = 93_040 + 3_240 * 42 + 240 * 33 + 80 * 20
+# Price + 161 Greeks per path: the forward pass above, then for each of the
+# 3,240 forward-steps in reverse (48 flops): the pre-step state and drift
+# factor from the stored step-final w (11), the suffix sum of the w adjoint,
+# the drift-factor adjoint and its derivative, the vega terms and rewinding
+# w (37); and the adjoint of the 80 payoffs (20 each).
+FLOPS_PER_PATH_LMM80_GREEKS = 93_040 + 3_240 * 48 + 80 * 20
 N_GREEKS_LMM80 = 2 * 80 + 1
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 
@@ -110,6 +110,39 @@ def cpu_baseline(model, N: int, seed: int, m_per_core: int):
                       f"({m_per_core} per thread), FP64, {dt:.1f} s"}
 
 
+def batch_leg(rq, I, torch, dev, n_cap: int, m_cap: int, steps: int):
+    """The 256-instrument batch (FP32 prices + Greeks) in one persistent
+    launch: whole-batch paths/s and the per-instrument completion times
+    (from the batch start) and spans, from the device real-time counter."""
+    import numpy as np
+    insts = I.cfg5()
+    if n_cap or m_cap:
+        import dataclasses
+        insts = [dataclasses.replace(c, N=min(c.N, n_cap or c.N), M=min(c.M, m_cap or c.M)) for c in insts]
+    paths = sum(c.N * c.M for c in insts)
+    ws = torch.empty(rq.batch_workspace(insts, "fp32", greeks=True), dtype=torch.uint8, device=dev)
+    rq.price_batch(insts, "fp32", greeks=True, device=dev, ws=ws)   # warm-up
+    torch.cuda.synchronize()
+    walls, br = [], None
+    for _ in range(max(1, steps)):
+        t0 = time.perf_counter()
+        br = rq.price_batch(insts, "fp32", greeks=True, device=dev, ws=ws)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+    hz = rq.realtime_hz()
+    tf = br.t_first.cpu().numpy().view(np.uint64).astype(np.float64)
+    tl = br.t_last.cpu().numpy().view(np.uint64).astype(np.float64)
+    done = (tl - tf.min()) / hz * 1e3
+    span = (tl - tf) / hz * 1e3
+    wall = float(np.median(walls))
+    return {"workload": "cfg5_256_instruments" + ("" if not (n_cap or m_cap) else f"_N<=2^{n_cap.bit_length() - 1}_M<={m_cap}"),
+            "n_instruments": len(insts), "paths": paths, "precision": "fp32", "greeks": True,
+            "paths_per_s": paths / wall, "ms_per_batch": wall * 1e3,
+            "kernel_span_ms": float((tl.max() - tf.min()) / hz * 1e3),
+            "completion_ms_p50": float(np.percentile(done, 50)), "completion_ms_p99": float(np.percentile(done, 99)),
+            "span_ms_p50": float(np.percentile(span, 50)), "span_ms_p99": float(np.percentile(span, 99))}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +152,8 @@ def main(argv=None):
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-m-per-core", type=int, default=4)
+    ap.add_argument("--batch", default="capped", choices=["capped", "full", "off"],
+                    help="256-instrument batch leg: N <= 2^14 and M <= 64 (capped), as drawn (full), or none")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
@@ -213,6 +248,9 @@ def main(argv=None):
                      "kernel": "lmm_adjoint_kernel<80,3,float>", "kernel_ms": kms_g},
     }
     line.update(out_extra)
+    if args.batch != "off":
+        caps = (1 << 14, 64) if args.batch == "capped" else (0, 0)
+        line["batch"] = batch_leg(rq, I, torch, dev, caps[0], caps[1], 3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(model, N, seed, args.cpu_m_per_core)
     print(json.dumps(line), flush=True)

@@ -194,6 +194,90 @@ rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t s
  * Values below 2^-64 in the fold min(u, 1-u) are clamped to it. */
 rq_status rq_inv_normal(int64_t n, const double *u, void *z, rq_precision prec, void *stream);
 
+/* ---- Batches of instruments ------------------------------------------------
+ * price_batch: many instruments (LIBOR books and MBS pools of any supported
+ * shape, each with its own N, M, seed, m_offset and flags) priced in ONE
+ * persistent launch.  Work items are (instrument, replication, block of 64
+ * paths); waves take them from an atomic queue, so small and large
+ * instruments share the GPU without a launch per instrument.  Each item
+ * writes its own partial sums, so the results do not depend on the tuning:
+ * for every instrument they are bit-identical to those of any other chunk,
+ * grid or order, and equal (to the rounding of the block sums) to what the
+ * single-instrument entry points return for it.  (Not in the paper: a
+ * serving form of the same method.) */
+enum { RQ_INST_LMM = 0, RQ_INST_MBS = 1 };
+
+typedef struct {
+    int kind;                     /* RQ_INST_LMM or RQ_INST_MBS */
+    const rq_lmm_model *lmm;      /* host, kind RQ_INST_LMM (NULL otherwise) */
+    const rq_mbs_params *mbs;     /* host, kind RQ_INST_MBS (NULL otherwise) */
+    int64_t N;                    /* points per replication */
+    int M;                        /* replications */
+    uint64_t seed;
+    int64_t m_offset;
+    int flags;                    /* RQ_START_ZERO / RQ_PERM_RANDOM */
+} rq_instrument;
+
+/* Launch shape of the batch (all fields 0 = automatic):
+ *   chunk         work items taken per queue grab (0: from the item count)
+ *   waves_per_cu  persistent blocks (one wave each) per compute unit (0: as
+ *                 many as are resident, from the occupancy calculator)
+ *   order         RQ_ORDER_COST: instruments in decreasing estimated cost
+ *                 (longest first); RQ_ORDER_GIVEN: the caller's order */
+enum { RQ_ORDER_COST = 0, RQ_ORDER_GIVEN = 1 };
+typedef struct {
+    int chunk;
+    int waves_per_cu;
+    int order;
+} rq_tuning;
+
+/* Workspace bytes for price_batch / autotune_batch with these arguments
+ * (0 if they would be rejected). */
+size_t rq_batch_workspace(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks);
+
+/* price_batch(inst[n_inst]): per instrument k, the results of
+ * rq_price_caplets / rq_price_mbs with the same arguments.
+ *   inst      host [n_inst], 1 <= n_inst <= 65536
+ *   tuning    NULL or a launch shape (see rq_tuning)
+ *   outs      host [n_inst] rq_result (device buffers as for the single
+ *             entry points: theta [M_k][n_out_k] required)
+ *   grads     host [n_inst] or NULL; with with_greeks, the Greeks of each
+ *             instrument (LIBOR: the 2 n_fwd + 1 of rq_price_caplets; MBS:
+ *             dPV/di0)
+ *   t_first, t_last  device [n_inst] uint64 or both NULL: the earliest start
+ *             and latest end of instrument k's work items, in ticks of the
+ *             device real-time counter (rq_realtime_hz)
+ * No per-path output.  Errors name the offending instrument. */
+rq_status rq_price_batch(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks,
+                         const rq_tuning *tuning, const rq_result *outs, const rq_result *grads,
+                         uint64_t *t_first, uint64_t *t_last, void *ws, size_t ws_bytes, void *stream);
+
+/* autotune_batch: times price_batch on this batch for a fixed set of launch
+ * shapes (chunk in {1, 2, 4, 8}; the resident and half the resident blocks
+ * per CU; both orders), one untimed run first, and returns the fastest in
+ * *best (and its time in ms in *best_ms unless NULL).  The outputs hold the
+ * last run's results.  Synchronises the stream. */
+rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks,
+                            const rq_result *outs, const rq_result *grads, rq_tuning *best, double *best_ms,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* Frequency (Hz) of the device real-time counter of the batch timestamps. */
+rq_status rq_realtime_hz(double *hz);
+
+/* lmm_pca_loadings: unit-row factor loadings for the LIBOR model, from the
+ * n_factors principal components of the forward correlation
+ * rho_ij = exp(-beta |T_i - T_j|), T_i = i delta (i = 1..n_fwd): with
+ * eigenpairs (lambda_f, e_f) in descending order, row i is
+ * (sqrt(lambda_f) e_f[i])_f rescaled to unit length, each e_f signed so
+ * that e_f[0] > 0.  (A model input, not part of the paper's method: the
+ * paper's caplet is one-factor; the multi-factor workloads use this
+ * reduction.)  Host computation (Jacobi rotations), no device work.
+ *   out   host [n_fwd][n_factors], row-major, written on RQ_OK
+ * Errors: RQ_ERANGE for n_fwd outside [1, RQ_MAX_FWD] or n_factors outside
+ * [1, min(RQ_MAX_FACTORS, n_fwd)]; RQ_EINVAL for delta <= 0, beta <= 0 or
+ * out == NULL. */
+rq_status rq_lmm_pca_loadings(int n_fwd, int n_factors, double delta, double beta, double *out);
+
 /* Kernel timing instrumentation.  Between rq_timer_begin and rq_timer_end
  * every entry point records a pair of HIP events on its stream around its
  * main path kernel (the LIBOR or MBS pricing kernel, or the sequence

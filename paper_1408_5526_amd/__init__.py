@@ -48,6 +48,20 @@ class rq_mbs_params(C.Structure):
                 ("K1", C.c_double), ("K2", C.c_double), ("K3", C.c_double), ("K4", C.c_double)]
 
 
+class rq_instrument(C.Structure):
+    _fields_ = [("kind", C.c_int), ("lmm", C.POINTER(rq_lmm_model)), ("mbs", C.POINTER(rq_mbs_params)),
+                ("N", C.c_int64), ("M", C.c_int), ("seed", C.c_uint64), ("m_offset", C.c_int64),
+                ("flags", C.c_int)]
+
+
+class rq_tuning(C.Structure):
+    _fields_ = [("chunk", C.c_int), ("waves_per_cu", C.c_int), ("order", C.c_int)]
+
+
+INST_LMM, INST_MBS = 0, 1
+ORDER_COST, ORDER_GIVEN = 0, 1
+
+
 class rq_result(C.Structure):
     _fields_ = [("theta", C.c_void_p), ("mean", C.c_void_p), ("sd", C.c_void_p),
                 ("se", C.c_void_p)]
@@ -88,6 +102,20 @@ def lib():
                                C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
     L.rq_inv_normal.restype = C.c_int
     L.rq_inv_normal.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    L.rq_batch_workspace.restype = C.c_size_t
+    L.rq_batch_workspace.argtypes = [C.POINTER(rq_instrument), C.c_int, C.c_int, C.c_int]
+    L.rq_price_batch.restype = C.c_int
+    L.rq_price_batch.argtypes = [C.POINTER(rq_instrument), C.c_int, C.c_int, C.c_int, C.POINTER(rq_tuning),
+                                 C.POINTER(rq_result), C.POINTER(rq_result), C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_size_t, C.c_void_p]
+    L.rq_autotune_batch.restype = C.c_int
+    L.rq_autotune_batch.argtypes = [C.POINTER(rq_instrument), C.c_int, C.c_int, C.c_int,
+                                    C.POINTER(rq_result), C.POINTER(rq_result), C.POINTER(rq_tuning),
+                                    C.POINTER(C.c_double), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.rq_realtime_hz.restype = C.c_int
+    L.rq_realtime_hz.argtypes = [C.POINTER(C.c_double)]
+    L.rq_lmm_pca_loadings.restype = C.c_int
+    L.rq_lmm_pca_loadings.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, C.POINTER(C.c_double)]
     L.rq_timer_begin.restype = C.c_int
     L.rq_timer_begin.argtypes = [C.c_int]
     L.rq_timer_end.restype = C.c_int
@@ -276,6 +304,130 @@ def price_mbs(params, N: int, M: int, seed: int, m_offset: int = 0, flags: int =
 
 
 # ---------------------------------------------------------------------------
+# batches of instruments (one persistent launch)
+# ---------------------------------------------------------------------------
+@dataclass
+class BatchResult:
+    """results[k] (and greeks in results[k].greeks) per instrument, in the
+    caller's order; t_first / t_last [n] int64 device tensors of real-time
+    counter ticks (rq_realtime_hz) when timestamps were requested."""
+    results: list
+    t_first: Optional[object] = None
+    t_last: Optional[object] = None
+
+
+class _BatchHost:
+    """C instrument array for a list of instruments (objects with kind
+    "lmm"/"mbs", model, N, M, seed and optional m_offset, flags); the host
+    model arrays stay referenced while this object lives."""
+
+    def __init__(self, instruments):
+        n = len(instruments)
+        self.keep = []
+        self.arr = (rq_instrument * max(n, 1))()
+        self.n = n
+        self.n_out, self.n_g = [], []
+        for k, ins in enumerate(instruments):
+            e = self.arr[k]
+            if ins.kind == "lmm":
+                h = _LmmHost(ins.model)
+                self.keep.append(h)
+                e.kind = INST_LMM
+                e.lmm = C.pointer(h.c)
+                self.n_out.append(ins.model.n_fwd + 1)
+                self.n_g.append(2 * ins.model.n_fwd + 1)
+            elif ins.kind == "mbs":
+                p = _mbs_c(ins.model)
+                self.keep.append(p)
+                e.kind = INST_MBS
+                e.mbs = C.pointer(p)
+                self.n_out.append(1)
+                self.n_g.append(1)
+            else:
+                raise ValueError(f"unknown instrument kind {ins.kind!r}")
+            e.N = int(ins.N)
+            e.M = int(ins.M)
+            e.seed = int(ins.seed)
+            e.m_offset = int(getattr(ins, "m_offset", 0))
+            e.flags = int(getattr(ins, "flags", 0))
+
+
+def batch_workspace(instruments, precision="fp32", greeks: bool = False) -> int:
+    h = _BatchHost(instruments)
+    n = lib().rq_batch_workspace(h.arr, h.n, _prec(precision), int(greeks))
+    if n == 0:
+        raise RqError(RQ_EINVAL, last_error())
+    return n
+
+
+def _batch_outputs(h, instruments, greeks, dev):
+    res, cres, gcres = [], (rq_result * max(h.n, 1))(), (rq_result * max(h.n, 1))()
+    for k, ins in enumerate(instruments):
+        r, c = _result(int(ins.M), h.n_out[k], dev)
+        cres[k] = c
+        if greeks:
+            g, gc = _result(int(ins.M), h.n_g[k], dev)
+            gcres[k] = gc
+            r.greeks = g
+        res.append(r)
+    return res, cres, gcres
+
+
+def price_batch(instruments, precision="fp32", greeks: bool = False, tuning=None,
+                timestamps: bool = True, device=None, ws=None) -> BatchResult:
+    """Price every instrument of the list in one persistent launch.
+    tuning: None (automatic) or (chunk, waves_per_cu, order)."""
+    torch = _torch()
+    dev = _device(device)
+    h = _BatchHost(instruments)
+    prec = _prec(precision)
+    res, cres, gcres = _batch_outputs(h, instruments, greeks, dev)
+    need = lib().rq_batch_workspace(h.arr, h.n, prec, int(greeks))
+    if need == 0:
+        raise RqError(RQ_EINVAL, last_error())
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    tf = tl = None
+    if timestamps:
+        tf = torch.empty(max(h.n, 1), dtype=torch.int64, device=dev)
+        tl = torch.empty(max(h.n, 1), dtype=torch.int64, device=dev)
+    tu = rq_tuning(*tuning) if tuning is not None else None
+    _check(lib().rq_price_batch(h.arr, h.n, prec, int(greeks), C.byref(tu) if tu is not None else None,
+                                cres, gcres if greeks else None,
+                                C.c_void_p(tf.data_ptr() if tf is not None else 0),
+                                C.c_void_p(tl.data_ptr() if tl is not None else 0),
+                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)))
+    return BatchResult(res, tf, tl)
+
+
+def autotune_batch(instruments, precision="fp32", greeks: bool = False, device=None, ws=None):
+    """(chunk, waves_per_cu, order) of the fastest launch shape for this
+    batch, and its time in ms (times every candidate shape once)."""
+    dev = _device(device)
+    h = _BatchHost(instruments)
+    prec = _prec(precision)
+    res, cres, gcres = _batch_outputs(h, instruments, greeks, dev)
+    need = lib().rq_batch_workspace(h.arr, h.n, prec, int(greeks))
+    if need == 0:
+        raise RqError(RQ_EINVAL, last_error())
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, dev)
+    best = rq_tuning()
+    ms = C.c_double(0.0)
+    _check(lib().rq_autotune_batch(h.arr, h.n, prec, int(greeks), cres, gcres if greeks else None,
+                                   C.byref(best), C.byref(ms), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream(dev)))
+    return (best.chunk, best.waves_per_cu, best.order), ms.value
+
+
+def realtime_hz() -> float:
+    """Frequency of the device real-time counter of the batch timestamps."""
+    hz = C.c_double(0.0)
+    _check(lib().rq_realtime_hz(C.byref(hz)))
+    return hz.value
+
+
+# ---------------------------------------------------------------------------
 # autograd wrappers: the Greeks come from the adjoint kernel (LIBOR) and the
 # pathwise tangent (MBS); backward only scales them by the incoming gradient
 # ---------------------------------------------------------------------------
@@ -355,6 +507,16 @@ def inv_normal(u, precision="fp64"):
     _check(lib().rq_inv_normal(u.numel(), C.c_void_p(u.data_ptr()), C.c_void_p(z.data_ptr()), prec,
                                _stream(u.device)))
     return z
+
+
+def lmm_pca_loadings(n_fwd: int, n_factors: int, delta: float, beta: float):
+    """Unit-row PCA loadings [n_fwd][n_factors] of rho_ij = exp(-beta|T_i - T_j|)
+    (host computation; returns a numpy array)."""
+    import numpy as np
+    out = np.zeros((n_fwd, n_factors), dtype=np.float64)
+    _check(lib().rq_lmm_pca_loadings(n_fwd, n_factors, delta, beta,
+                                     out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
 
 
 def timer_begin(max_launches: int = 1000) -> None:

@@ -2,6 +2,7 @@
 // workspace layout and the launch sequence of every entry point.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -410,7 +411,7 @@ std::vector<uint8_t> adj_table(const rq_lmm_model *m)
         }
         r[6] = (T)(log2e * (-0.5 * a2 * m->delta));
         r[7] = (T)std::log2(m->delta * m->L0[n]);
-        r[8] = (T)(log2e * m->delta * a2);
+        r[8] = (T)sg;
         r[15] = (T)(log2e * m->delta * sg * b2);
     }
     std::vector<uint8_t> out(t.size() * sizeof(T));
@@ -453,6 +454,24 @@ std::vector<uint8_t> mbs_table(const rq_mbs_params *p)
     return out;
 }
 
+// Model scalars of the MBS kernel arguments: K0, the level payment c and
+// its derivative dc/di0.
+void mbs_scalars(const rq_mbs_params *params, rq::MbsArgs &a)
+{
+    a.i0 = params->i0;
+    a.sig = params->sigma;
+    a.K0 = std::exp(-0.5 * params->sigma * params->sigma);
+    a.K1 = params->K1;
+    a.K2 = params->K2;
+    a.K3 = params->K3;
+    a.K4 = params->K4;
+    const double vK = std::pow(1.0 + params->i0, -(double)params->months);
+    a.c = params->i0 / (1.0 - vK);
+    // dc/di0 with dv/di0 = -K (1+i0)^{-K-1}
+    const double dvK = -params->months * vK / (1.0 + params->i0);
+    a.dc = ((1.0 - vK) + params->i0 * dvK) / ((1.0 - vK) * (1.0 - vK));
+}
+
 rq_status finish(const rq_result *out, const double *partial, int stride, int off, int M, int n_blk,
                  int n_out, int64_t N, hipStream_t st)
 {
@@ -476,6 +495,350 @@ rq_status finish(const rq_result *out, const double *partial, int stride, int of
         f.n_out = n_out;
         RQ_HIP(rq::launch_finalize(f, st));
     }
+    return RQ_OK;
+}
+
+// ---- batch of instruments ------------------------------------------------------
+
+// Per-instrument plan: validated shape, tables and workspace offsets.
+struct InstPlan {
+    int kind = 0, s = 0, D = 0, nf = 0, months = 0;
+    int64_t N = 0;
+    int M = 0;
+    uint64_t seed = 0;
+    int64_t m_offset = 0;
+    int flags = 0;
+    Geometry g;
+    int n_blk = 0, n_out = 0, n_g = 0;   // n_g: Greek outputs per replication
+    double cost = 0.0;
+    size_t perm_elems = 0, model_bytes = 0, adj_off = 0;
+    size_t o_base = 0, o_perm = 0, o_model = 0, o_starts = 0, o_part = 0, part_g = 0;
+    int64_t setup_units = 0;
+};
+
+struct BatchPlan {
+    std::vector<InstPlan> ip;   // caller order
+    std::vector<int> order;     // execution position -> caller index
+    int n_red = 0;              // reduce / finalize entries
+    size_t o_inst = 0, o_item0 = 0, o_setup = 0, o_setup_pf = 0, o_red = 0, o_red_pf = 0, o_fin = 0,
+           o_fin_pf = 0, o_queue = 0;
+    size_t host_bytes = 0, o_wtop = 0, wtop_bytes = 0, total = 0;
+    int64_t n_items = 0, setup_total = 0, red_blocks = 0;
+    bool any_lmm = false;
+};
+
+constexpr int kBatchMaxInst = 1 << 16;
+
+rq_status plan_batch(const rq_instrument *inst, int n_inst, rq_precision prec, bool greeks, int order,
+                     BatchPlan &bp)
+{
+    if (!inst) return fail(RQ_EINVAL, "instrument list is NULL");
+    if (n_inst < 1 || n_inst > kBatchMaxInst) return fail(RQ_ERANGE, "n_inst = %d outside [1, %d]", n_inst, kBatchMaxInst);
+    if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
+    if (order != RQ_ORDER_COST && order != RQ_ORDER_GIVEN) return fail(RQ_EINVAL, "unknown order %d", order);
+    const auto &pr = primes();
+    bp.ip.assign(n_inst, InstPlan());
+    for (int k = 0; k < n_inst; ++k) {
+        const rq_instrument &I = inst[k];
+        InstPlan &p = bp.ip[k];
+        rq_status st;
+        p.kind = I.kind;
+        p.N = I.N;
+        p.M = I.M;
+        p.seed = I.seed;
+        p.m_offset = I.m_offset;
+        p.flags = I.flags;
+        if (I.flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "instrument %d: RQ_OUT_DIGITS applies to rq_sequence only", k);
+        if (I.kind == RQ_INST_LMM) {
+            if ((st = check_lmm(I.lmm))) return fail(st, "instrument %d: %s", k, g_err.c_str());
+            p.nf = I.lmm->n_fwd;
+            p.D = I.lmm->n_factors;
+            p.s = p.nf * p.D;
+            p.n_out = p.nf + 1;
+            p.n_g = greeks ? 2 * p.nf + 1 : 0;
+            const double fs = 0.5 * p.nf * (p.nf + 1.0);
+            p.cost = fs * (6.0 * p.D + 8.0) * (greeks ? 3.0 : 1.0) + p.s * 40.0;
+            bp.any_lmm = true;
+        } else if (I.kind == RQ_INST_MBS) {
+            if ((st = check_mbs(I.mbs))) return fail(st, "instrument %d: %s", k, g_err.c_str());
+            p.months = I.mbs->months;
+            p.s = p.months;
+            p.n_out = 1;
+            p.n_g = greeks ? 1 : 0;
+            p.cost = p.months * (greeks ? 110.0 : 80.0);
+        } else {
+            return fail(RQ_EINVAL, "instrument %d: unknown kind %d", k, I.kind);
+        }
+        if ((st = check_common(p.s, p.N, p.M, p.flags, p.m_offset, p.g)))
+            return fail(st, "instrument %d: %s", k, g_err.c_str());
+        p.n_blk = (int)((p.N + rq::kWave - 1) / rq::kWave);
+        if ((int64_t)p.n_blk * p.M >= (1ll << 31)) return fail(RQ_ERANGE, "instrument %d: N*M too large", k);
+        p.cost *= (double)p.N * (double)p.M;
+        p.perm_elems = 0;
+        if (p.flags & RQ_PERM_RANDOM)
+            for (int j = 0; j < p.s; ++j) p.perm_elems += pr[j];
+        if (p.kind == RQ_INST_LMM) {
+            const size_t rows = (size_t)lmm_rows(p.nf);
+            p.adj_off = rows * (rq::kFwdRow * sizeof(double) + rq::kRow32 * sizeof(float));
+            p.model_bytes = p.adj_off + rows * rq::kAdjRow * (prec == RQ_FP32 ? sizeof(float) : sizeof(double));
+        } else {
+            p.model_bytes = 2 * (size_t)(p.months + 1) * sizeof(double);
+        }
+        p.setup_units = (int64_t)p.M * p.g.n_seg * p.s;
+    }
+    bp.order.resize(n_inst);
+    for (int k = 0; k < n_inst; ++k) bp.order[k] = k;
+    if (order == RQ_ORDER_COST)   // largest first (LPT); ties keep the caller's order
+        std::stable_sort(bp.order.begin(), bp.order.end(),
+                         [&](int x, int y) { return bp.ip[x].cost > bp.ip[y].cost; });
+    // reduce / finalize entries: prices of every instrument, then Greeks
+    bp.n_red = n_inst * (greeks ? 2 : 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o += al(bytes); return at; };
+    bp.o_inst = take(sizeof(rq::BatchInst) * n_inst);
+    bp.o_item0 = take(sizeof(int64_t) * (n_inst + 1));
+    bp.o_setup = take(sizeof(rq::SetupArgs) * n_inst);
+    bp.o_setup_pf = take(sizeof(int64_t) * (n_inst + 1));
+    bp.o_red = take(sizeof(rq::ReduceArgs) * bp.n_red);
+    bp.o_red_pf = take(sizeof(int64_t) * (bp.n_red + 1));
+    bp.o_fin = take(sizeof(rq::FinalizeArgs) * bp.n_red);
+    bp.o_fin_pf = take(sizeof(int64_t) * (bp.n_red + 1));
+    bp.o_queue = take(sizeof(unsigned long long));
+    for (int k = 0; k < n_inst; ++k) {
+        InstPlan &p = bp.ip[k];
+        p.o_base = take(sizeof(BaseEnt) * (size_t)p.s);
+        p.o_perm = take(p.perm_elems * sizeof(uint16_t));
+        p.o_model = take(p.model_bytes);
+    }
+    bp.host_bytes = o;
+    bp.n_items = 0;
+    bp.setup_total = 0;
+    bp.red_blocks = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        InstPlan &p = bp.ip[k];
+        p.o_starts = take(sizeof(StartEnt) * (size_t)p.setup_units);
+        const size_t rows = (size_t)p.M * p.n_blk;
+        if (p.kind == RQ_INST_LMM) {
+            p.o_part = take(rows * (p.n_out + p.n_g) * sizeof(double));
+            p.part_g = rows * p.n_out;   // Greek rows follow the price rows
+        } else {
+            p.o_part = take(rows * (greeks ? 2 : 1) * sizeof(double));
+        }
+        bp.n_items += (int64_t)rows;
+        bp.setup_total += p.setup_units;
+        bp.red_blocks += (int64_t)p.M * (greeks ? 2 : 1);
+    }
+    bp.wtop_bytes = (greeks && bp.any_lmm)
+                        ? (size_t)rq::kBatchMaxSlots * rq::kBatchSlotElems * (prec == RQ_FP32 ? 4 : 8)
+                        : 0;
+    bp.o_wtop = take(bp.wtop_bytes);
+    bp.total = o;
+    return RQ_OK;
+}
+
+int device_cus()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return n;
+}
+
+rq_status run_batch(const rq_instrument *inst, int n_inst, rq_precision prec, bool greeks, const rq_tuning *tuning,
+                    const rq_result *outs, const rq_result *grads, uint64_t *t_first, uint64_t *t_last, void *ws,
+                    size_t ws_bytes, hipStream_t st)
+{
+    rq_tuning tu{0, 0, RQ_ORDER_COST};
+    if (tuning) {
+        tu = *tuning;
+        if (tu.chunk < 0 || tu.chunk > 4096) return fail(RQ_EINVAL, "tuning.chunk = %d outside [0, 4096]", tu.chunk);
+        if (tu.waves_per_cu < 0 || tu.waves_per_cu > 32)
+            return fail(RQ_EINVAL, "tuning.waves_per_cu = %d outside [0, 32]", tu.waves_per_cu);
+    }
+    BatchPlan bp;
+    rq_status stt;
+    if ((stt = plan_batch(inst, n_inst, prec, greeks, tu.order, bp))) return stt;
+    if (!outs) return fail(RQ_EINVAL, "outs is NULL");
+    if (greeks && !grads) return fail(RQ_EINVAL, "grads is NULL with Greeks requested");
+    if ((t_first == nullptr) != (t_last == nullptr)) return fail(RQ_EINVAL, "t_first and t_last go together");
+    for (int k = 0; k < n_inst; ++k) {
+        if (!outs[k].theta) return fail(RQ_EINVAL, "outs[%d].theta is NULL", k);
+        if (greeks && !grads[k].theta) return fail(RQ_EINVAL, "grads[%d].theta is NULL", k);
+    }
+    if ((stt = check_ws(ws, ws_bytes, bp.total))) return stt;
+    const bool f32 = prec == RQ_FP32;
+    const int cus = device_cus();
+    if (cus <= 0) return fail(RQ_EHIP, "cannot query the device's compute units");
+    int per_cu = tu.waves_per_cu;
+    if (per_cu == 0) per_cu = rq::batch_blocks_per_cu(f32, greeks);
+    if (per_cu <= 0) return fail(RQ_EHIP, "occupancy query of the batch kernel failed");
+    int64_t grid = (int64_t)cus * per_cu;
+    if (greeks && bp.any_lmm && grid > rq::kBatchMaxSlots) grid = rq::kBatchMaxSlots;
+    if (grid > bp.n_items) grid = bp.n_items;
+    int chunk = tu.chunk;
+    if (chunk == 0) {   // about 16 grabs per block, at most 8 items a grab
+        const int64_t c = bp.n_items / (grid * 16);
+        chunk = (int)std::max<int64_t>(1, std::min<int64_t>(8, c));
+    }
+
+    uint8_t *w = (uint8_t *)ws;
+    std::vector<uint8_t> host(bp.host_bytes, 0);
+    auto *bi = reinterpret_cast<rq::BatchInst *>(host.data() + bp.o_inst);
+    auto *item0 = reinterpret_cast<int64_t *>(host.data() + bp.o_item0);
+    auto *sa = reinterpret_cast<rq::SetupArgs *>(host.data() + bp.o_setup);
+    auto *spf = reinterpret_cast<int64_t *>(host.data() + bp.o_setup_pf);
+    auto *ra = reinterpret_cast<rq::ReduceArgs *>(host.data() + bp.o_red);
+    auto *rpf = reinterpret_cast<int64_t *>(host.data() + bp.o_red_pf);
+    auto *fa = reinterpret_cast<rq::FinalizeArgs *>(host.data() + bp.o_fin);
+    auto *fpf = reinterpret_cast<int64_t *>(host.data() + bp.o_fin_pf);
+    int64_t items = 0, su = 0, rb = 0, fu = 0;
+    for (int e = 0; e < n_inst; ++e) {
+        const int k = bp.order[e];
+        const InstPlan &p = bp.ip[k];
+        const rq_instrument &I = inst[k];
+        // host tables of this instrument
+        PointTables pt;
+        if ((stt = build_point_tables(p.s, p.g, p.seed, p.flags, pt))) return fail(stt, "instrument %d: %s", k, g_err.c_str());
+        std::memcpy(host.data() + p.o_base, pt.base.data(), sizeof(BaseEnt) * pt.base.size());
+        if (!pt.perm.empty()) std::memcpy(host.data() + p.o_perm, pt.perm.data(), pt.perm.size() * sizeof(uint16_t));
+        std::vector<uint8_t> tab;
+        if (p.kind == RQ_INST_LMM) {
+            tab = lmm_table(I.lmm);
+            tab.resize(p.adj_off, 0);
+            std::vector<uint8_t> at = f32 ? adj_table<float>(I.lmm) : adj_table<double>(I.lmm);
+            tab.insert(tab.end(), at.begin(), at.end());
+        } else {
+            tab = mbs_table(I.mbs);
+        }
+        std::memcpy(host.data() + p.o_model, tab.data(), std::min(tab.size(), p.model_bytes));
+        // geometry of the points, shared by both kinds
+        Layout L;
+        L.base = p.o_base;
+        L.perm = p.o_perm;
+        L.model = p.o_model;
+        L.starts = p.o_starts;
+        L.partial = p.o_part;
+        const rq::SeqGeom sg = seq_geom(L, p.g, w, p.s, p.M, p.N, p.flags);
+        rq::BatchInst &d = bi[e];
+        std::memset(&d, 0, sizeof d);
+        d.kind = p.kind;
+        d.n_factors = p.D;
+        d.slot = k;
+        double *part = reinterpret_cast<double *>(w + p.o_part);
+        if (p.kind == RQ_INST_LMM) {
+            rq::LmmArgs &a = d.lmm;
+            a.g = sg;
+            a.fwd = reinterpret_cast<const double *>(w + p.o_model);
+            a.fwd32 = reinterpret_cast<const float *>(w + p.o_model + (size_t)lmm_rows(p.nf) * rq::kFwdRow * sizeof(double));
+            a.adj = w + p.o_model + p.adj_off;
+            a.wtop = greeks ? (void *)(w + bp.o_wtop) : nullptr;
+            a.n_slots = 0;
+            a.partial = part;
+            a.partial_g = greeks ? part + p.part_g : nullptr;
+            a.n_g = p.n_g;
+            a.per_path = nullptr;
+            a.n_fwd = p.nf;
+            a.n_out = p.n_out;
+            a.n_blk = p.n_blk;
+            a.delta = I.lmm->delta;
+            a.sqrt_delta = std::sqrt(I.lmm->delta);
+            a.num0 = 1.0 + I.lmm->delta * I.lmm->L0[0];
+        } else {
+            rq::MbsArgs &a = d.mbs;
+            a.g = sg;
+            a.ck = reinterpret_cast<const double *>(w + p.o_model);
+            a.partial = part;
+            a.per_path = nullptr;
+            a.months = p.months;
+            a.n_blk = p.n_blk;
+            a.n_part = greeks ? 2 : 1;
+            mbs_scalars(I.mbs, a);
+        }
+        item0[e] = items;
+        items += (int64_t)p.M * p.n_blk;
+        // setup of the start table
+        rq::SetupArgs &s = sa[e];
+        s.base_dev = reinterpret_cast<BaseEnt *>(w + p.o_base);
+        s.starts = reinterpret_cast<StartEnt *>(w + p.o_starts);
+        s.perm = (p.flags & RQ_PERM_RANDOM) ? reinterpret_cast<const uint16_t *>(w + p.o_perm) : nullptr;
+        s.seed = p.seed;
+        s.m_offset = p.m_offset;
+        s.s = p.s;
+        s.M = p.M;
+        s.n_seg = p.g.n_seg;
+        s.S = p.g.S;
+        s.flags = p.flags;
+        spf[e] = su;
+        su += p.setup_units;
+    }
+    item0[n_inst] = items;
+    spf[n_inst] = su;
+    // reductions: prices (caller order), then Greeks
+    for (int r = 0; r < bp.n_red; ++r) {
+        const int k = r % n_inst;
+        const bool gr = r >= n_inst;
+        const InstPlan &p = bp.ip[k];
+        const rq_result &res = gr ? grads[k] : outs[k];
+        const double *part = reinterpret_cast<const double *>(w + p.o_part);
+        rq::ReduceArgs &a = ra[r];
+        a.theta = res.theta;
+        a.M = p.M;
+        a.n_blk = p.n_blk;
+        a.Nd = (double)p.N;
+        if (p.kind == RQ_INST_LMM) {
+            a.partial = gr ? part + p.part_g : part;
+            a.n_out = gr ? p.n_g : p.n_out;
+            a.stride = a.n_out;
+            a.off = 0;
+        } else {
+            a.partial = part;
+            a.n_out = 1;
+            a.stride = greeks ? 2 : 1;
+            a.off = gr ? 1 : 0;
+        }
+        rpf[r] = rb;
+        rb += p.M;
+        rq::FinalizeArgs &f = fa[r];
+        f.theta = res.theta;
+        f.mean = res.mean;
+        f.sd = res.sd;
+        f.se = res.se;
+        f.M = p.M;
+        f.n_out = a.n_out;
+        fpf[r] = fu;
+        if (res.mean || res.sd || res.se) fu += a.n_out;
+    }
+    rpf[bp.n_red] = rb;
+    fpf[bp.n_red] = fu;
+
+    RQ_HIP(hipMemcpyAsync(w, host.data(), host.size(), hipMemcpyHostToDevice, st));
+    rq::BatchSetup bs{reinterpret_cast<const rq::SetupArgs *>(w + bp.o_setup),
+                      reinterpret_cast<const int64_t *>(w + bp.o_setup_pf), n_inst};
+    RQ_HIP(rq::launch_batch_setup(bs, su, st));
+    auto *queue = reinterpret_cast<unsigned long long *>(w + bp.o_queue);
+    RQ_HIP(rq::launch_batch_init(queue, reinterpret_cast<unsigned long long *>(t_first),
+                                 reinterpret_cast<unsigned long long *>(t_last), t_first ? n_inst : 0, st));
+    rq::BatchArgs ba;
+    ba.inst = reinterpret_cast<const rq::BatchInst *>(w + bp.o_inst);
+    ba.item0 = reinterpret_cast<const int64_t *>(w + bp.o_item0);
+    ba.n_inst = n_inst;
+    ba.chunk = chunk;
+    ba.n_items = items;
+    ba.queue = queue;
+    ba.t_first = reinterpret_cast<unsigned long long *>(t_first);
+    ba.t_last = reinterpret_cast<unsigned long long *>(t_last);
+    ba.n_caller = n_inst;
+    ba.wtop = greeks ? (void *)(w + bp.o_wtop) : nullptr;
+    {
+        TimedRegion tr(st);
+        RQ_HIP(rq::launch_batch(ba, (int)grid, f32, greeks, st));
+    }
+    rq::BatchReduce br{reinterpret_cast<const rq::ReduceArgs *>(w + bp.o_red),
+                       reinterpret_cast<const int64_t *>(w + bp.o_red_pf), bp.n_red};
+    RQ_HIP(rq::launch_batch_reduce(br, rb, st));
+    rq::BatchFinalize bf{reinterpret_cast<const rq::FinalizeArgs *>(w + bp.o_fin),
+                         reinterpret_cast<const int64_t *>(w + bp.o_fin_pf), bp.n_red};
+    RQ_HIP(rq::launch_batch_finalize(bf, fu, st));
     return RQ_OK;
 }
 
@@ -568,8 +931,12 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
 }
 
 // Model-region bytes and partial-region bytes of a LIBOR call.
+// Adjoint: persistent grid size and the byte offset of its stored-w slots
+// inside the partial region.
+static int adj_slots(int64_t tasks) { return (int)std::min<int64_t>(tasks, rq::kAdjSlots); }
+
 static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greeks, size_t &mb, size_t &pb,
-                         int &n_blk)
+                         int &n_blk, size_t *wtop_off = nullptr)
 {
     const int rows = lmm_rows(model->n_fwd);
     const int n_out = model->n_fwd + 1;
@@ -578,7 +945,11 @@ static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greek
     if (greeks) {
         mb += (size_t)rows * rq::kAdjRow * sizeof(double);   // room for either precision
         n_blk = adj_blocks(N);
-        pb = (size_t)M * n_blk * (n_out + n_g) * sizeof(double);
+        pb = al((size_t)M * n_blk * (n_out + n_g) * sizeof(double));
+        if (wtop_off) *wtop_off = pb;
+        // room for FP64 slots: [slots][n_fwd][d][64]
+        pb += (size_t)adj_slots((int64_t)M * n_blk) * model->n_fwd * model->n_factors * rq::kAdjBlockHost *
+              sizeof(double);
     } else {
         n_blk = lmm_blocks(N);
         pb = (size_t)M * n_blk * n_out * sizeof(double);
@@ -613,9 +984,9 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     Geometry g;
     if ((stt = check_common(s, N, M, flags, m_offset, g))) return stt;
     const bool greeks = grad != nullptr;
-    size_t mb, pb;
+    size_t mb, pb, wtop_off = 0;
     int n_blk;
-    caplet_sizes(model, N, M, greeks, mb, pb, n_blk);
+    caplet_sizes(model, N, M, greeks, mb, pb, n_blk, &wtop_off);
     const int n_out = model->n_fwd + 1;
     const int n_g = 2 * model->n_fwd + 1;
     if ((int64_t)n_blk * M >= (1ll << 31)) return fail(RQ_ERANGE, "N*M too large for one launch");
@@ -638,6 +1009,8 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     a.fwd = reinterpret_cast<const double *>(w + L.model);
     a.fwd32 = reinterpret_cast<const float *>(w + L.model + (size_t)lmm_rows(model->n_fwd) * rq::kFwdRow * sizeof(double));
     a.adj = greeks ? (const void *)(w + L.model + adj_off) : nullptr;
+    a.wtop = greeks ? (void *)(w + L.partial + wtop_off) : nullptr;
+    a.n_slots = greeks ? adj_slots((int64_t)M * n_blk) : 0;
     a.partial = reinterpret_cast<double *>(w + L.partial);
     a.partial_g = greeks ? a.partial + (size_t)M * n_blk * n_out : nullptr;
     a.n_g = n_g;
@@ -702,24 +1075,169 @@ rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t s
     a.months = params->months;
     a.n_blk = n_blk;
     a.n_part = n_part;
-    a.i0 = params->i0;
-    a.sig = params->sigma;
-    a.K0 = std::exp(-0.5 * params->sigma * params->sigma);
-    a.K1 = params->K1;
-    a.K2 = params->K2;
-    a.K3 = params->K3;
-    a.K4 = params->K4;
-    const double vK = std::pow(1.0 + params->i0, -(double)params->months);
-    a.c = params->i0 / (1.0 - vK);
-    // dc/di0 with dv/di0 = -K (1+i0)^{-K-1}
-    const double dvK = -params->months * vK / (1.0 + params->i0);
-    a.dc = ((1.0 - vK) + params->i0 * dvK) / ((1.0 - vK) * (1.0 - vK));
+    mbs_scalars(params, a);
     {
         TimedRegion tr(st);
         RQ_HIP(rq::launch_mbs(a, prec == RQ_FP32, st));
     }
     if ((stt = finish(out, a.partial, n_part, 0, M, n_blk, 1, N, st))) return stt;
     if (grad) return finish(grad, a.partial, n_part, 1, M, n_blk, 1, N, st);
+    return RQ_OK;
+}
+
+rq_status rq_lmm_pca_loadings(int n_fwd, int n_factors, double delta, double beta, double *out)
+{
+    if (n_fwd < 1 || n_fwd > RQ_MAX_FWD) return fail(RQ_ERANGE, "n_fwd = %d outside [1, %d]", n_fwd, RQ_MAX_FWD);
+    if (n_factors < 1 || n_factors > RQ_MAX_FACTORS || n_factors > n_fwd)
+        return fail(RQ_ERANGE, "n_factors = %d outside [1, min(%d, n_fwd)]", n_factors, RQ_MAX_FACTORS);
+    if (!(delta > 0.0) || !std::isfinite(delta)) return fail(RQ_EINVAL, "delta must be > 0");
+    if (!(beta > 0.0) || !std::isfinite(beta)) return fail(RQ_EINVAL, "beta must be > 0");
+    if (!out) return fail(RQ_EINVAL, "out is NULL");
+    const int n = n_fwd;
+    // rho_ij = exp(-beta |T_i - T_j|), T_i = (i+1) delta; cyclic Jacobi
+    // rotations diagonalise it (A -> V^T A V, V accumulating the rotations)
+    std::vector<double> A((size_t)n * n), V((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        V[(size_t)i * n + i] = 1.0;
+        for (int j = 0; j < n; ++j) A[(size_t)i * n + j] = std::exp(-beta * delta * std::abs(i - j));
+    }
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; ++i) {
+            diag += A[(size_t)i * n + i] * A[(size_t)i * n + i];
+            for (int j = i + 1; j < n; ++j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        }
+        if (off <= 1e-34 * diag) break;
+        for (int p = 0; p < n - 1; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                // rotation angle: tan(2 phi) = 2 a_pq / (a_qq - a_pp), |phi| <= pi/4
+                const double th = (aqq - app) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::abs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {   // columns p, q
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {   // rows p, q
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+        }
+    }
+    // the n_factors largest eigenvalues, descending
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(),
+              [&](int x, int y) { return A[(size_t)x * n + x] > A[(size_t)y * n + y]; });
+    for (int f = 0; f < n_factors; ++f) {
+        const int e = idx[f];
+        const double lam = A[(size_t)e * n + e];
+        if (!(lam > 0.0)) return fail(RQ_EINVAL, "correlation matrix is not positive definite");
+        const double sg = V[e] < 0.0 ? -1.0 : 1.0;   // first component positive
+        const double sl = std::sqrt(lam);
+        for (int i = 0; i < n; ++i) out[(size_t)i * n_factors + f] = sg * V[(size_t)i * n + e] * sl;
+    }
+    for (int i = 0; i < n; ++i) {   // unit rows: forward i's total vol is sigma_i
+        double r = 0.0;
+        for (int f = 0; f < n_factors; ++f) r += out[(size_t)i * n_factors + f] * out[(size_t)i * n_factors + f];
+        r = std::sqrt(r);
+        for (int f = 0; f < n_factors; ++f) out[(size_t)i * n_factors + f] /= r;
+    }
+    return RQ_OK;
+}
+
+size_t rq_batch_workspace(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks)
+{
+    BatchPlan bp;
+    if (plan_batch(inst, n_inst, prec, with_greeks != 0, RQ_ORDER_COST, bp) != RQ_OK) return 0;
+    return bp.total;
+}
+
+rq_status rq_price_batch(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks,
+                         const rq_tuning *tuning, const rq_result *outs, const rq_result *grads, uint64_t *t_first,
+                         uint64_t *t_last, void *ws, size_t ws_bytes, void *stream)
+{
+    return run_batch(inst, n_inst, prec, with_greeks != 0, tuning, outs, grads, t_first, t_last, ws, ws_bytes,
+                     (hipStream_t)stream);
+}
+
+rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks,
+                            const rq_result *outs, const rq_result *grads, rq_tuning *best, double *best_ms,
+                            void *ws, size_t ws_bytes, void *stream)
+{
+    if (!best) return fail(RQ_EINVAL, "best is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const bool greeks = with_greeks != 0;
+    {   // validate everything before the first launch
+        BatchPlan bp;
+        rq_status s0 = plan_batch(inst, n_inst, prec, greeks, RQ_ORDER_COST, bp);
+        if (s0) return s0;
+    }
+    const int occ = rq::batch_blocks_per_cu(prec == RQ_FP32, greeks);
+    if (occ <= 0) return fail(RQ_EHIP, "occupancy query of the batch kernel failed");
+    std::vector<rq_tuning> cand;
+    const int chunks[] = {1, 2, 4, 8};
+    const int orders[] = {RQ_ORDER_COST, RQ_ORDER_GIVEN};
+    std::vector<int> per_cu = {occ};
+    if (occ > 1) per_cu.push_back(occ / 2);
+    for (int o : orders)
+        for (int pc : per_cu)
+            for (int c : chunks) cand.push_back(rq_tuning{c, pc, o});
+    hipEvent_t e0, e1;
+    RQ_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(RQ_EHIP, "hipEventCreate failed");
+    }
+    double bms = INFINITY;
+    rq_tuning bt = cand[0];
+    // one untimed run (first touch of the workspace, code load), then each
+    // candidate once
+    rq_status stt = run_batch(inst, n_inst, prec, greeks, &cand[0], outs, grads, nullptr, nullptr, ws, ws_bytes, st);
+    for (size_t c = 0; stt == RQ_OK && c < cand.size(); ++c) {
+        if (hipEventRecord(e0, st) != hipSuccess) {
+            stt = fail(RQ_EHIP, "hipEventRecord failed");
+            break;
+        }
+        stt = run_batch(inst, n_inst, prec, greeks, &cand[c], outs, grads, nullptr, nullptr, ws, ws_bytes, st);
+        if (stt != RQ_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            stt = fail(RQ_EHIP, "timing the batch failed");
+            break;
+        }
+        if (ms < bms) {
+            bms = ms;
+            bt = cand[c];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (stt != RQ_OK) return stt;
+    *best = bt;
+    if (best_ms) *best_ms = bms;
+    return RQ_OK;
+}
+
+rq_status rq_realtime_hz(double *hz)
+{
+    if (!hz) return fail(RQ_EINVAL, "hz is NULL");
+    int dev = 0, khz = 0;
+    RQ_HIP(hipGetDevice(&dev));
+    RQ_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    *hz = 1000.0 * (double)khz;
     return RQ_OK;
 }
 

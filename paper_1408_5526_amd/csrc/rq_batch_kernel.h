@@ -1,0 +1,100 @@
+// rq_batch_kernel.h -- one persistent launch over every work item of a
+// batch of instruments (LIBOR books of 1..80 forwards and 1..3 factors, and
+// MBS pools), in a fixed precision, with or without Greeks.
+//
+// Each block is one wave.  It takes `chunk` consecutive items at a time from
+// an atomic queue (one vector atomic by lane 0) until the queue runs dry,
+// so every wave reaches the exit.  The instrument of an item is found by a
+// binary search over item0 (wave-uniform scalar loads); its kind and factor
+// count select the path code, so all branches are wave-uniform.  LIBOR
+// items run the task of rq_lmm_adj.h at the full forward capacity (forwards
+// beyond n_fwd are skipped by uniform branches); MBS items the task of
+// rq_mbs.h.  Every item writes its own partial row, so results do not
+// depend on which wave ran it: they are bit-identical for any chunk, grid
+// or instrument order.  Per instrument, lane 0 records the earliest start
+// and latest end (s_memrealtime ticks) of its items with atomic min/max.
+#pragma once
+
+#include "rq_lmm_adj.h"
+#include "rq_mbs.h"
+
+namespace rq {
+
+template <typename T, bool GREEKS>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && GREEKS ? 2 : 1)))
+void batch_kernel(BatchArgs b)
+{
+    __shared__ T vbar[kMaxFwd][kWave];
+    const int lane = threadIdx.x;
+    T *wt = GREEKS ? (T *)b.wtop + (size_t)blockIdx.x * kBatchSlotElems + lane : nullptr;
+    const cptr<int64_t> item0 = as_const<int64_t>(b.item0);
+    const cptr<BatchInst> inst = as_const<BatchInst>(b.inst);
+#pragma unroll 1
+    for (;;) {
+        unsigned long long got = 0ull;
+        if (lane == 0) got = atomicAdd(b.queue, (unsigned long long)b.chunk);
+        // every lane is active here: the first active lane is lane 0
+        const int64_t start = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(got >> 32)) << 32) |
+                                        (uint64_t)__builtin_amdgcn_readfirstlane((unsigned)got));
+        if (start >= b.n_items) break;
+        const int64_t end = start + b.chunk < b.n_items ? start + b.chunk : b.n_items;
+#pragma unroll 1
+        for (int64_t it = start; it < end; ++it) {
+            int lo = 0, hi = b.n_inst;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (item0[mid] <= it) lo = mid;
+                else hi = mid;
+            }
+            const int64_t local = it - item0[lo];
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+            if (inst[lo].kind == kInstLmm) {
+                const LmmArgs a = load_uniform<LmmArgs>(&b.inst[lo].lmm);
+                const int m = (int)(local / a.n_blk);
+                const int blk = (int)(local - (int64_t)m * a.n_blk);
+                switch (inst[lo].n_factors) {
+                case 1: lmm_task<kMaxFwd, 1, T, GREEKS>(a, m, blk, local, wt, vbar); break;
+                case 2: lmm_task<kMaxFwd, 2, T, GREEKS>(a, m, blk, local, wt, vbar); break;
+                default: lmm_task<kMaxFwd, 3, T, GREEKS>(a, m, blk, local, wt, vbar); break;
+                }
+            } else {
+                const MbsArgs a = load_uniform<MbsArgs>(&b.inst[lo].mbs);
+                const int m = (int)(local / a.n_blk);
+                const int blk = (int)(local - (int64_t)m * a.n_blk);
+                mbs_task<T, GREEKS>(a, m, blk, local);
+            }
+            const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+            const int slot = inst[lo].slot;
+            if (lane == 0 && b.t_first) {
+                atomicMin(b.t_first + slot, (unsigned long long)t0);
+                atomicMax(b.t_last + slot, (unsigned long long)t1);
+            }
+        }
+    }
+}
+
+template <typename T, bool GREEKS>
+static hipError_t launch_batch_t(const BatchArgs &b, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_kernel<T, GREEKS>), dim3((unsigned)grid), dim3(kWave), 0, st, b);
+    return hipGetLastError();
+}
+
+template <typename T, bool GREEKS>
+static int batch_blocks_per_cu_t()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<T, GREEKS>, kWave, 0) != hipSuccess) return 0;
+    return n;
+}
+
+hipError_t launch_batch_f32p(const BatchArgs &b, int grid, hipStream_t st);
+hipError_t launch_batch_f32g(const BatchArgs &b, int grid, hipStream_t st);
+hipError_t launch_batch_f64p(const BatchArgs &b, int grid, hipStream_t st);
+hipError_t launch_batch_f64g(const BatchArgs &b, int grid, hipStream_t st);
+int batch_occ_f32p();
+int batch_occ_f32g();
+int batch_occ_f64p();
+int batch_occ_f64g();
+
+}  // namespace rq

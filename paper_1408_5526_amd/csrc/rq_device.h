@@ -293,6 +293,21 @@ __device__ __forceinline__ cptr<T> as_const(const void *p)
     return (cptr<T>)p;
 }
 
+// A wave-uniform struct read through the constant address space (scalar
+// loads; the fields the caller never uses are not loaded).
+template <typename S>
+__device__ __forceinline__ S load_uniform(const void *p)
+{
+    static_assert(sizeof(S) % 4 == 0, "struct size must be a multiple of 4");
+    const cptr<uint32_t> q = as_const<uint32_t>(p);
+    uint32_t w[sizeof(S) / 4];
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(S) / 4; ++i) w[i] = q[i];
+    S out;
+    __builtin_memcpy(&out, w, sizeof(S));
+    return out;
+}
+
 __device__ __forceinline__ void acc_add(Acc &a, double x)
 {
     const double t = a.s + x;

@@ -96,7 +96,7 @@ constexpr int kGrp = 4;   // forwards per branch-free group of the LIBOR kernel
 
 // Adjoint table, kAdjRow entries per forward in the kernel's precision:
 //   [0..2] log2(e) a_n     [3..5] delta a_n     [6] log2(e) c_n
-//   [7]    log2(delta L_n(0))                    [8] q_n = log2(e) delta |a_n|^2
+//   [7]    log2(delta L_n(0))                    [8] sigma_n
 //   [9..11] log2(e) b_n    [12..14] delta b_n   [15] log2(e) delta sigma_n |b_n|^2
 // where b_n = a_n / sigma_n is the unit loading row.
 constexpr int kAdjRow = 16;
@@ -106,6 +106,8 @@ struct LmmArgs {
     const double *fwd;       // [n_fwd][kFwdRow]
     const float *fwd32;      // [n_fwd][kRow32]
     const void *adj;         // [n_fwd][kAdjRow] (FP32 or FP64) or nullptr
+    void *wtop;              // adjoint: [n_slots][n_fwd][d][64] step-final w, kernel precision
+    int n_slots;             // adjoint: blocks of the persistent grid
     double *partial_g;       // [M][n_blk][n_g] Greek partial sums or nullptr
     int n_g;                 // 2 n_fwd + 1
     double *partial;         // [M][n_blk][n_out]
@@ -146,7 +148,8 @@ hipError_t launch_setup(const SetupArgs &a, hipStream_t st);
 hipError_t launch_sequence(const SeqGeom &g, int flags, void *out, hipStream_t st);
 hipError_t launch_lmm(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
 hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
-constexpr int kAdjBlockHost = 128;   // threads per block of the adjoint kernel
+constexpr int kAdjBlockHost = 64;    // paths per block of the adjoint kernel (one wave)
+constexpr int kAdjSlots = 2048;      // adjoint grid: 256 CUs x 8 resident waves
 hipError_t launch_mbs(const MbsArgs &a, int fp32, hipStream_t st);   // n_part == 2: tangent
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);
@@ -154,5 +157,63 @@ hipError_t launch_inv_normal(int64_t n, const double *u, void *z, int fp32, hipS
 
 // Largest forward count of the compiled LIBOR kernels.
 constexpr int kMaxFwd = 80;
+
+// ---- batch of instruments (one persistent launch over all work items) ----
+// A work item is one 64-path block of one replication of one instrument.
+// Items are numbered instrument by instrument in the execution order;
+// instrument k owns [item0[k], item0[k+1]).
+constexpr int kInstLmm = 0;
+constexpr int kInstMbs = 1;
+constexpr int kBatchSlotElems = kMaxFwd * 3 * kWave;   // stored-w slot, elements
+constexpr int kBatchMaxSlots = 2048;                     // blocks of a Greeks batch
+
+struct BatchInst {
+    LmmArgs lmm;             // kind LMM: n_blk counts 64-path blocks
+    MbsArgs mbs;             // kind MBS: n_blk counts 64-path blocks
+    int kind;
+    int n_factors;           // LMM
+    int slot;                // index of the instrument in the caller's list
+    int pad0;
+};
+
+struct BatchArgs {
+    const BatchInst *inst;   // [n_inst], execution order
+    const int64_t *item0;    // [n_inst + 1]
+    int n_inst;
+    int chunk;               // items taken per queue grab
+    int64_t n_items;
+    unsigned long long *queue;                  // next free item (zeroed by batch_init)
+    unsigned long long *t_first, *t_last;       // [n_caller] s_memrealtime ticks, or nullptr
+    int n_caller;
+    void *wtop;              // Greeks: [grid][kBatchSlotElems] kernel precision
+};
+
+// Batched setup / reductions: argument arrays with an exclusive prefix of
+// the per-entry unit counts (threads, blocks or outputs), prefix[n] = total.
+struct BatchSetup {
+    const SetupArgs *args;
+    const int64_t *prefix;   // units = M * n_seg * s
+    int n;
+};
+struct BatchReduce {
+    const ReduceArgs *args;
+    const int64_t *prefix;   // units = M (one block each)
+    int n;
+};
+struct BatchFinalize {
+    const FinalizeArgs *args;
+    const int64_t *prefix;   // units = n_out (one thread each; args with no output pointer count 0)
+    int n;
+};
+
+hipError_t launch_batch_init(unsigned long long *queue, unsigned long long *t_first, unsigned long long *t_last,
+                             int n_caller, hipStream_t st);
+hipError_t launch_batch_setup(const BatchSetup &b, int64_t total, hipStream_t st);
+hipError_t launch_batch_reduce(const BatchReduce &b, int64_t blocks, hipStream_t st);
+hipError_t launch_batch_finalize(const BatchFinalize &b, int64_t total, hipStream_t st);
+hipError_t launch_batch(const BatchArgs &b, int grid, int fp32, int greeks, hipStream_t st);
+// Resident blocks per CU of the batch kernel for (fp32, greeks), from the
+// occupancy calculator.
+int batch_blocks_per_cu(int fp32, int greeks);
 
 }  // namespace rq

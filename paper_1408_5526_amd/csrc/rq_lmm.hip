@@ -95,10 +95,10 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a)
                 for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
                 // form the (small) step increment first, then add it to the
                 // O(1) state once: one rounding at the state's scale per step
-                float e = q[0] * w[0];
+                float e = ffma(q[0], w[0], q[6]);
 #pragma unroll
                 for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
-                X[n] = ffma(e + q[6], on, X[n]);
+                X[n] = ffma(e, on, X[n]);
             } else {
                 const double dl = delta * X[n];
                 const double g = dl / (1.0 + dl);

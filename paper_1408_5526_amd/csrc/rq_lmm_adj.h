@@ -2,43 +2,44 @@
 // hand-written adjoint (reverse-mode) sweep, one path per lane.
 //
 // Forward pass (same scheme as rq_lmm.hip, state X_n = log2(L_n / L_n(0))):
-//   step k:  w = sqrt(delta) z_k;  for n = k..n_fwd-1:
+//   step k:  w = sqrt(delta) z_k;  for n = k..n_fwd-1 in ascending order:
 //     g_n = G(X_n) = 1 / (1 + 2^{-(X_n + l_n)}),  l_n = log2(delta L_n(0))
-//     w  += g_n delta a_n
-//     X_n += log2(e) (c_n + a_n . w)
+//     w  += g_n delta a_n                       (w is now w_n)
+//     X_n += log2(e) (c_n + a_n . w_n)
+//   and the lane stores the step's final w (d numbers) in its block's slot.
 // Payoffs (FP64): L_n(T_n) = L_n(0) 2^{X_n}; P_n = delta (L_n - K_n)^+ / num_{n+1},
 //   num_{n+1} = num_0 prod_{j<=n} (1 + delta L_j(T_j)); book = sum_n P_n.
 //
 // Reverse sweep.  The payoff adjoint is
 //   dbook/dL_n(T_n) = delta [L_n > K_n] / num_{n+1} - delta / (1 + delta L_n) * sum_{j>=n} P_j
-// and Xbar_n = dbook/dL_n(T_n) * L_n(T_n) ln 2.  Steps then run backwards.  The
-// pre-step state of step k is not stored: it is recovered from the post-step
-// state.  With C = X_post - log2(e) c_n - log2(e) a_n . w_{n-1} and
-// q_n = log2(e) delta |a_n|^2 >= 0, the pre-state solves
-//   y + q_n G(y) = C,
-// whose left side is strictly increasing.  Newton from y0 = C - q_n G(X_post)
-// converges quadratically (FP32: one step, FP64: two).  Ascending n rebuilds
-// the states and w; descending n then applies the adjoint of each
-// forward-step:
-//   Wbar += Xbar_n log2(e) a_n           (adjoint of w_n, a suffix sum over n)
-//   gbar  = delta a_n . Wbar
+// and Xbar_n = dbook/dL_n(T_n) * L_n(T_n) ln 2.  Steps then run backwards,
+// k = n_fwd-1..0.  Step k restarts from its stored final w and visits its
+// forwards in descending order.  With w_n known, the pre-step state and the
+// drift factor are explicit (nothing is solved, no normal is drawn again):
+//   X_n -= log2(e) (c_n + a_n . w_n),   g_n = G(X_n)
+// and the adjoint of the forward-step is
+//   Wbar += Xbar_n log2(e) a_n            (adjoint of w_n: a suffix sum over n)
 //   vega_n += Xbar_n log2(e) (b_n . w_n - delta sigma_n |b_n|^2) + g_n delta b_n . Wbar
-//   Xbar_n += gbar G'(X_n),  G' = ln2 G (1 - G)
-//   w    -= g_n delta a_n                (back to w_{n-1})
+//   Xbar_n += (delta a_n . Wbar) G'(X_n),  G' = ln2 G (1 - G)
+//   w    -= g_n delta a_n                 (back to w_{n-1})
 // After step 0, Xbar_n is the adjoint of log2 L_n(0), so
 //   dbook/dL_n(0) = Xbar_n / (L_n(0) ln 2);  dbook/dL_0(0) = -delta book / num_0.
+// The reconstructed states differ from the forward pass's by rounding only
+// (one rounding of the increment per step, as in the forward pass).
 //
 // Per path: n_fwd+1 prices (caplets, book) and 2 n_fwd + 1 Greeks (deltas,
-// spot delta, vegas), reduced like the pricing kernel (wave transpose
-// butterfly, fixed block order).  State and adjoint state live in registers;
-// the vega accumulators live in LDS ([forward][lane], conflict-free).
+// spot delta, vegas).  A block is one wave of 64 paths; the grid is
+// persistent (a fixed number of blocks strides over the replications' path
+// blocks), so the per-block slot for the stored w is bounded by the grid, not
+// by N M.  State and adjoint state live in registers, the vega accumulators
+// in LDS ([forward][lane], conflict-free; before the sweep the same rows
+// hold the payoff adjoint).  Outputs are wave sums (transpose
+// butterfly), one partial row per path block: deterministic.
 #pragma once
 
 #include "rq_device.h"
 
 namespace rq {
-
-constexpr int kAdjBlock = 128;   // two waves; LDS holds the vega accumulators
 
 template <typename T> __device__ __forceinline__ T adj_exp2(T x);
 template <> __device__ __forceinline__ float adj_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -47,36 +48,41 @@ template <typename T> __device__ __forceinline__ T adj_rcp(T x);
 template <> __device__ __forceinline__ float adj_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ __forceinline__ double adj_rcp<double>(double x) { return 1.0 / x; }
 
-template <int NFC, int D, typename T>
-__global__ __launch_bounds__(kAdjBlock) void lmm_adjoint_kernel(LmmArgs a)
+// One task: the 64 paths of block `blk` of replication m (task = m n_blk + blk
+// indexes the partial rows).  GREEKS = false runs the forward pass and the
+// payoffs only (the batch kernel's pricing form).  wt is the lane's entry of
+// the block's stored-w slot; vbar the block's LDS rows.
+template <int NFC, int D, typename T, bool GREEKS>
+__device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64_t task, T *__restrict__ wt,
+                                         T (&vbar)[NFC][kWave])
 {
-    static_assert(NFC % 16 == 0, "capacity must be a multiple of 16");
+    static_assert(NFC % 16 == 0 && NFC % kGrp == 0, "capacity must be a multiple of 16");
     constexpr bool kF32 = sizeof(T) == 4;
     constexpr T kLn2 = T(0.69314718055994530942);
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wave = tid / kWave;
-    const int m = blockIdx.x / a.n_blk;
-    const int blk = blockIdx.x - m * a.n_blk;
-    const int64_t i = (int64_t)blk * kAdjBlock + tid;
-    const bool active = i < a.g.N;
-    const int seg = (int)(((int64_t)blk * kAdjBlock) >> a.g.log2S);
-    const uint32_t t = (uint32_t)(i - ((int64_t)seg << a.g.log2S));
-    const StartEnt *__restrict__ st = a.g.starts + ((size_t)m * a.g.n_seg + seg) * a.g.s;
-    const double *__restrict__ fwd = a.fwd;
-    const T *__restrict__ adj = (const T *)a.adj;
+    const int lane = threadIdx.x;
+    const cptr<double> fwd = as_const<double>(a.fwd);
+    const cptr<T> tab = as_const<T>(a.adj);
     const int nf = a.n_fwd;
     const double delta = a.delta;
     const T sqd = (T)a.sqrt_delta;
 
-    __shared__ T vbar[NFC][kAdjBlock];
-    __shared__ double red[kAdjBlock / kWave][3 * NFC];
-    __shared__ double red2[kAdjBlock / kWave][2];
-
     auto r64 = [&](int n, int c) -> double { return fwd[n * kFwdRow + c]; };
-    auto ra = [&](int n, int c) -> T { return adj[n * kAdjRow + c]; };
-    auto G = [&](int n, T y) -> T { return adj_rcp<T>(T(1) + adj_exp2<T>(-(y + ra(n, 7)))); };
-    auto normals = [&](int k, T (&w)[D]) {
+    auto G = [&](T s) -> T { return adj_rcp<T>(T(1) + adj_exp2<T>(-s)); };
+
+    const int64_t i = (int64_t)blk * kWave + lane;
+    const bool active = i < a.g.N;
+    const int seg = (int)(((int64_t)blk * kWave) >> a.g.log2S);   // blocks never straddle segments
+    const uint32_t t = (uint32_t)(i - ((int64_t)seg << a.g.log2S));
+    const StartEnt *__restrict__ st = a.g.starts + ((size_t)m * a.g.n_seg + seg) * a.g.s;
+
+    T X[NFC], Xb[NFC];
+#pragma unroll
+    for (int n = 0; n < NFC; ++n) X[n] = T(0);
+
+    // ---- forward pass ----
+#pragma unroll 1
+    for (int k = 0; k < nf; ++k) {
+        T w[D];
 #pragma unroll
         for (int f = 0; f < D; ++f) {
             const int j = k * D + f;
@@ -85,44 +91,55 @@ __global__ __launch_bounds__(kAdjBlock) void lmm_adjoint_kernel(LmmArgs a)
                                          : radinv_x<false, !kF32>(c, st + j, t, a.g.perm);
             w[f] = sqd * inv_normal(x, T(0));
         }
-    };
-
-    T X[NFC], Xb[NFC];
+        // one forward-step; on = 0 leaves a dead forward and w unchanged
+        auto body = [&](int n, T on) __attribute__((always_inline)) {
+            const cptr<T> q = tab + n * kAdjRow;
+            const T g = G(X[n] + q[7]) * on;
 #pragma unroll
-    for (int n = 0; n < NFC; ++n) {
-        X[n] = T(0);
-        Xb[n] = T(0);
-        vbar[n][tid] = T(0);
-    }
-
-    // ---- forward pass ----
-#pragma unroll 1
-    for (int k = 0; k < nf; ++k) {
-        T w[D];
-        normals(k, w);
+            for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
+            // the (small) increment log2(e) (c_n + a_n . w) is formed first and
+            // added to the O(1) state once
+            T e = ffma(q[0], w[0], q[6]);
+#pragma unroll
+            for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
+            X[n] = ffma(e, on, X[n]);
+        };
         const unsigned alive = (unsigned)(nf - k);
+        if constexpr (kF32) {
 #pragma unroll
-        for (int n = 0; n < NFC; ++n) {
-            if ((unsigned)(n - k) < alive) {
-                const T g = G(n, X[n]);
+            for (int gq = 0; gq < NFC / kGrp; ++gq) {
+                const int n0 = gq * kGrp;
+                if (n0 + kGrp > k && n0 < nf) {
 #pragma unroll
-                for (int f = 0; f < D; ++f) w[f] = ffma(g, ra(n, 3 + f), w[f]);
-                T e = ra(n, 0) * w[0];
-#pragma unroll
-                for (int f = 1; f < D; ++f) e = ffma(ra(n, f), w[f], e);
-                X[n] += e + ra(n, 6);
+                    for (int u = 0; u < kGrp; ++u)
+                        body(n0 + u, __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                         (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)));
+                }
             }
+        } else {
+#pragma unroll
+            for (int n = 0; n < NFC; ++n)
+                if ((unsigned)(n - k) < alive) body(n, T(1));
+        }
+        if constexpr (GREEKS) {
+#pragma unroll
+            for (int f = 0; f < D; ++f) wt[(size_t)(k * D + f) * kWave] = w[f];
         }
     }
 
     // ---- payoffs and their adjoint (FP64) ----
-    // pass 1: the book; pass 2 (16 forwards at a time): payoffs again, their
-    // wave sums, and the adjoint of the fixing values
+    // With Greeks, pass 1 forms the book and pass 2 (16 forwards at a time)
+    // the payoffs again, their wave sums, and the adjoint of the fixing
+    // values, parked in the (not yet used) vega rows of LDS so that the
+    // state registers are not doubled while the FP64 payoff work needs
+    // registers.  Without Greeks only pass 2 runs.
     const double act = active ? 1.0 : 0.0;
     double *pp = (a.per_path && active) ? a.per_path + ((size_t)m * (size_t)a.g.N + (size_t)i) * a.n_out
                                         : nullptr;
+    double *out = a.partial + (size_t)task * a.n_out;
+    double *gout = GREEKS ? a.partial_g + (size_t)task * a.n_g : nullptr;
     double book = 0.0;
-    {
+    if constexpr (GREEKS) {
         double num = a.num0;
 #pragma unroll
         for (int n = 0; n < NFC; ++n) {
@@ -152,82 +169,107 @@ __global__ __launch_bounds__(kAdjBlock) void lmm_adjoint_kernel(LmmArgs a)
                         const double ex = Lf - r64(n, 8);
                         const bool itm = r64(n, 9) != 0.0 && ex > 0.0;
                         if (itm) Pn = delta * ex / num;
-                        double dL = -delta / onep * (book - before);
-                        if (itm) dL += delta / num;
-                        Xb[n] = (T)(dL * Lf * 0.69314718055994530942);
-                        before += Pn;
+                        if constexpr (GREEKS) {
+                            double dL = -delta / onep * (book - before);
+                            if (itm) dL += delta / num;
+                            vbar[n][lane] = (T)(dL * Lf * 0.69314718055994530942);
+                            before += Pn;
+                        } else {
+                            book += Pn;
+                        }
                         if (pp) pp[n] = Pn;
                     }
                     V[q] = Pn * act;
                 }
                 const double sv = wave_sum16(V, lane);
-                if ((lane & 3) == 0) red[wave][c * 16 + (lane >> 2)] = sv;
+                const int o = c * 16 + (lane >> 2);
+                if ((lane & 3) == 0 && o < nf) out[o] = sv;
             }
         }
     }
     if (pp) pp[nf] = book;
+    {
+        const double b = wave_sum(book * act);
+        const double sp = GREEKS ? wave_sum(-delta * book / a.num0 * act) : 0.0;
+        if (lane == 0) {
+            out[nf] = b;
+            if (GREEKS) gout[nf] = sp;
+        }
+    }
+    if constexpr (!GREEKS) return;
 
     // ---- reverse sweep ----
+#pragma unroll
+    for (int n = 0; n < NFC; ++n) {
+        Xb[n] = n < nf ? vbar[n][lane] : T(0);
+        vbar[n][lane] = T(0);
+    }
+    T wn[D];
+#pragma unroll
+    for (int f = 0; f < D; ++f) wn[f] = wt[(size_t)((nf - 1) * D + f) * kWave];
 #pragma unroll 1
     for (int k = nf - 1; k >= 0; --k) {
-        T w[D];
-        normals(k, w);
-        const unsigned alive = (unsigned)(nf - k);
-        // ascending: rebuild the pre-step states and w
+        T w[D], Wb[D];
 #pragma unroll
-        for (int n = 0; n < NFC; ++n) {
-            if ((unsigned)(n - k) < alive) {
-                T C = X[n] - ra(n, 6);
-#pragma unroll
-                for (int f = 0; f < D; ++f) C = ffma(-ra(n, f), w[f], C);
-                const T q = ra(n, 8);
-                T y = C - q * G(n, X[n]);
-#pragma unroll
-                for (int it = 0; it < (kF32 ? 1 : 2); ++it) {
-                    const T gy = G(n, y);
-                    const T h = y + q * gy - C;
-                    const T dh = T(1) + q * kLn2 * gy * (T(1) - gy);
-                    y -= h * adj_rcp<T>(dh);
-                }
-                X[n] = y;
-                const T g = G(n, y);
-#pragma unroll
-                for (int f = 0; f < D; ++f) w[f] = ffma(g, ra(n, 3 + f), w[f]);
-            }
+        for (int f = 0; f < D; ++f) {
+            w[f] = wn[f];
+            Wb[f] = T(0);
         }
-        // descending: adjoint of each forward-step
-        T Wb[D];
+        if (k > 0) {   // prefetch the next (earlier) step's final w
 #pragma unroll
-        for (int f = 0; f < D; ++f) Wb[f] = T(0);
+            for (int f = 0; f < D; ++f) wn[f] = wt[(size_t)((k - 1) * D + f) * kWave];
+        }
+        // adjoint of one forward-step, w = w_n on entry, w_{n-1} on exit;
+        // on = 0 leaves everything unchanged
+        // (a_n = sigma_n b_n, so a_n . w = sigma_n b_n . w and
+        // delta a_n . Wbar = sigma_n delta b_n . Wbar: two dot products serve
+        // the state, the vega and the drift-factor adjoint)
+        auto body = [&](int n, T on) __attribute__((always_inline)) {
+            const cptr<T> q = tab + n * kAdjRow;
+            T bw = q[9] * w[0];                       // log2(e) b_n . w_n
 #pragma unroll
-        for (int nn = 0; nn < NFC; ++nn) {
-            const int n = NFC - 1 - nn;
-            if ((unsigned)(n - k) < alive) {
-                const T g = G(n, X[n]);
-                const T xb = Xb[n];
-                T bw = T(0), dbw = T(0), gb = T(0);
+            for (int f = 1; f < D; ++f) bw = ffma(q[9 + f], w[f], bw);
+            const T y = ffma(-ffma(q[8], bw, q[6]), on, X[n]);
+            X[n] = y;
+            const T g = G(y + q[7]);
+            const T ge = g * on;
+            const T xb = Xb[n] * on;
 #pragma unroll
-                for (int f = 0; f < D; ++f) {
-                    Wb[f] = ffma(xb, ra(n, f), Wb[f]);
-                    bw = ffma(ra(n, 9 + f), w[f], bw);
+            for (int f = 0; f < D; ++f) Wb[f] = ffma(xb, q[f], Wb[f]);
+            T dbw = q[12] * Wb[0];                    // delta b_n . Wbar
+#pragma unroll
+            for (int f = 1; f < D; ++f) dbw = ffma(q[12 + f], Wb[f], dbw);
+            const T h = ge * dbw;
+            vbar[n][lane] += ffma(xb, bw - q[15], h);
+            Xb[n] = ffma(q[8] * h, ffma(-kLn2, g, kLn2), Xb[n]);
+#pragma unroll
+            for (int f = 0; f < D; ++f) w[f] = ffma(-ge, q[3 + f], w[f]);
+        };
+        const unsigned alive = (unsigned)(nf - k);
+        if constexpr (kF32) {
+#pragma unroll
+            for (int gq = NFC / kGrp - 1; gq >= 0; --gq) {
+                const int n0 = gq * kGrp;
+                if (n0 + kGrp > k && n0 < nf) {
+#pragma unroll
+                    for (int u = kGrp - 1; u >= 0; --u)
+                        body(n0 + u, __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                         (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)));
                 }
-#pragma unroll
-                for (int f = 0; f < D; ++f) {
-                    dbw = ffma(ra(n, 12 + f), Wb[f], dbw);
-                    gb = ffma(ra(n, 3 + f), Wb[f], gb);
-                }
-                vbar[n][tid] += ffma(xb, bw - ra(n, 15), g * dbw);
-                Xb[n] = ffma(gb * kLn2 * g, T(1) - g, xb);
-#pragma unroll
-                for (int f = 0; f < D; ++f) w[f] = ffma(-g, ra(n, 3 + f), w[f]);
             }
+        } else {
+#pragma unroll
+            for (int n = NFC - 1; n >= 0; --n)
+                if ((unsigned)(n - k) < alive) body(n, T(1));
         }
     }
 
-    // ---- Greeks [2 nf + 1]: deltas, spot delta, vegas ----
+    // ---- Greeks [2 nf + 1]: deltas, spot delta (above), vegas ----
 #pragma unroll
     for (int c = 0; c < NFC / 16; ++c) {
         if (c * 16 < nf) {
+            const int o = c * 16 + (lane >> 2);
+            const bool wr = (lane & 3) == 0 && o < nf;
             double V[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -235,43 +277,40 @@ __global__ __launch_bounds__(kAdjBlock) void lmm_adjoint_kernel(LmmArgs a)
                 V[q] = n < nf ? (double)Xb[n] / (r64(n, 7) * 0.69314718055994530942) * act : 0.0;
             }
             double s = wave_sum16(V, lane);
-            if ((lane & 3) == 0) red[wave][NFC + c * 16 + (lane >> 2)] = s;
+            if (wr) gout[o] = s;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int n = c * 16 + q;
-                V[q] = n < nf ? (double)vbar[n][tid] * act : 0.0;
+                V[q] = n < nf ? (double)vbar[n][lane] * act : 0.0;
             }
             s = wave_sum16(V, lane);
-            if ((lane & 3) == 0) red[wave][2 * NFC + c * 16 + (lane >> 2)] = s;
+            if (wr) gout[nf + 1 + o] = s;
         }
     }
-    {
-        const double b = wave_sum(book * act);
-        const double sp = wave_sum(-delta * book / a.num0 * act);
-        if (lane == 0) {
-            red2[wave][0] = b;
-            red2[wave][1] = sp;
-        }
-    }
-    __syncthreads();
-    double *out = a.partial + ((size_t)m * a.n_blk + blk) * a.n_out;
-    double *gout = a.partial_g + ((size_t)m * a.n_blk + blk) * a.n_g;
-    for (int o = tid; o < nf; o += kAdjBlock) {
-        out[o] = red[0][o] + red[1][o];
-        gout[o] = red[0][NFC + o] + red[1][NFC + o];
-        gout[nf + 1 + o] = red[0][2 * NFC + o] + red[1][2 * NFC + o];
-    }
-    if (tid == 0) {
-        out[nf] = red2[0][0] + red2[1][0];
-        gout[nf] = red2[0][1] + red2[1][1];
+}
+
+// FP32: the compiler is asked for two waves per SIMD (at most 256 registers);
+// the few values it then spills are outside the time loops.
+template <int NFC, int D, typename T>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
+void lmm_adjoint_kernel(LmmArgs a)
+{
+    __shared__ T vbar[NFC][kWave];
+    // this block's slot of stored step-final w: [k][f][lane]
+    T *wt = (T *)a.wtop + (size_t)blockIdx.x * ((size_t)a.n_fwd * D * kWave) + threadIdx.x;
+    const int64_t tasks = (int64_t)a.g.M * a.n_blk;
+#pragma unroll 1
+    for (int64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
+        const int m = (int)(task / a.n_blk);
+        const int blk = (int)(task - (int64_t)m * a.n_blk);
+        lmm_task<NFC, D, T, true>(a, m, blk, task, wt, vbar);
     }
 }
 
 template <int NFC, int D, typename T>
 static hipError_t launch_adj_t(const LmmArgs &a, hipStream_t st)
 {
-    const int64_t blocks = (int64_t)a.n_blk * a.g.M;
-    hipLaunchKernelGGL((lmm_adjoint_kernel<NFC, D, T>), dim3((unsigned)blocks), dim3(kAdjBlock), 0, st, a);
+    hipLaunchKernelGGL((lmm_adjoint_kernel<NFC, D, T>), dim3((unsigned)a.n_slots), dim3(kWave), 0, st, a);
     return hipGetLastError();
 }
 

@@ -99,3 +99,26 @@ def test_python_api_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError, match="no GPU"):
         rq.sequence(2, 8, 1, 1)
+
+
+@pytest.mark.parametrize("n,d,delta,beta", [(80, 3, 0.25, 0.1), (20, 2, 0.25, 0.1), (33, 1, 0.5, 0.3),
+                                            (3, 3, 0.25, 2.0), (1, 1, 0.25, 0.1)])
+def test_pca_loadings_match_numpy_eigh(n, d, delta, beta):
+    # host-only entry: the same reduction as the model inputs (numpy eigh)
+    got = rq.lmm_pca_loadings(n, d, delta, beta)
+    want = I.pca_loadings(np.arange(1, n + 1) * delta, beta, d)
+    assert np.abs(got - want).max() < 1e-12
+    assert np.allclose(np.linalg.norm(got, axis=1), 1.0, rtol=0, atol=1e-15)
+
+
+def test_pca_loadings_validation():
+    out = (C.c_double * 16)()
+    lib = rq.lib()
+    assert lib.rq_lmm_pca_loadings(0, 1, 0.25, 0.1, out) == rq.RQ_ERANGE
+    assert lib.rq_lmm_pca_loadings(81, 1, 0.25, 0.1, out) == rq.RQ_ERANGE
+    assert lib.rq_lmm_pca_loadings(2, 3, 0.25, 0.1, out) == rq.RQ_ERANGE
+    assert lib.rq_lmm_pca_loadings(4, 4, 0.25, 0.1, out) == rq.RQ_ERANGE
+    assert lib.rq_lmm_pca_loadings(4, 2, 0.0, 0.1, out) == rq.RQ_EINVAL
+    assert lib.rq_lmm_pca_loadings(4, 2, 0.25, 0.0, out) == rq.RQ_EINVAL
+    assert lib.rq_lmm_pca_loadings(4, 2, 0.25, 0.1, None) == rq.RQ_EINVAL
+    assert "NULL" in rq.last_error()

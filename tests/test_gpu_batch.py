@@ -1,0 +1,183 @@
+"""GPU checks of the batch entry point (one persistent launch over many
+instruments, work taken from an atomic queue).
+
+Bars:
+  * FP64 estimates of every instrument against the oracle on the same seeded
+    inputs, to the single-instrument bar |gpu - o| <= 1e-12 (|o| + scale);
+  * FP32 estimates within 1e-6 relative of the oracle at N >= 4096;
+  * with Greeks, every instrument's estimates and Greeks equal those of the
+    single-instrument entry point (same per-path code, block sums in the
+    same or a different fixed order) to 1e-13 relative;
+  * results are bit-identical for every launch shape (chunk, blocks per CU,
+    instrument order), since each work item writes its own partial row;
+  * timestamps bracket every instrument's work.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1408_5526_amd as rq
+import rqmc_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@dataclasses.dataclass
+class Ins:
+    kind: str
+    model: object
+    N: int
+    M: int
+    seed: int
+    m_offset: int = 0
+    flags: int = 0
+
+
+def _mixed():
+    return [
+        Ins("lmm", I.small_lmm(6, 2), 1000, 3, 17),
+        Ins("mbs", I.mbs_paper(60), 700, 2, 6),
+        Ins("lmm", I.lmm_curve80(20, 3), 513, 2, 5, flags=rq.PERM_RANDOM),
+        Ins("lmm", I.cfg1().model, 300, 4, 1),
+        Ins("mbs", I.mbs_paper(120, 0.03), 257, 3, 4, m_offset=5, flags=rq.PERM_RANDOM),
+        Ins("lmm", I.lmm_curve80(80, 3), 130, 2, 3, m_offset=7),
+        Ins("lmm", I.lmm_curve80(33, 1), 64, 1, 9, flags=rq.START_ZERO),
+        Ins("mbs", I.mbs_paper(1), 1, 1, 2),
+    ]
+
+
+def _oracle(ins):
+    if ins.kind == "lmm":
+        return O.price_caplets(ins.model, ins.N, ins.M, ins.seed, m_offset=ins.m_offset, flags=ins.flags)
+    return O.price_mbs(ins.model, ins.N, ins.M, ins.seed, m_offset=ins.m_offset, flags=ins.flags)
+
+
+def _scale(ins):
+    if ins.kind == "lmm":
+        s = ins.model.delta * np.nan_to_num(np.asarray(ins.model.strike, dtype=np.float64), nan=0.0)
+        return np.append(s, s.sum())
+    return np.ones(1)
+
+
+def test_batch_fp64_matches_oracle_per_instrument():
+    batch = _mixed()
+    _say("batch fp64", len(batch))
+    br = rq.price_batch(batch, precision="fp64")
+    for k, ins in enumerate(batch):
+        th_o = _oracle(ins)
+        th_g = _np(br.results[k].theta)
+        sc = _scale(ins)
+        assert (np.abs(th_g - th_o) <= 1e-12 * (np.abs(th_o) + sc)).all(), k
+        mo, so, eo = O.finalize(th_o)
+        assert np.allclose(_np(br.results[k].mean), mo, rtol=1e-12, atol=1e-12 * sc.max()), k
+        if ins.M > 1:
+            assert np.allclose(_np(br.results[k].sd), so, rtol=1e-9, atol=1e-13 * sc.max()), k
+        else:
+            assert np.isnan(_np(br.results[k].sd)).all()
+
+
+def test_batch_fp32_matches_oracle():
+    batch = [Ins("lmm", I.lmm_curve80(20, 3), 4200, 2, 5), Ins("mbs", I.mbs_paper(120), 4097, 2, 4),
+             Ins("lmm", I.small_lmm(6, 2), 4133, 3, 17, flags=rq.PERM_RANDOM)]
+    _say("batch fp32")
+    br = rq.price_batch(batch, precision="fp32")
+    for k, ins in enumerate(batch):
+        th_o = _oracle(ins)
+        live = np.abs(th_o) > 0
+        rel = np.abs(_np(br.results[k].theta) - th_o)[live] / np.abs(th_o)[live]
+        _say("batch fp32 instrument", k, "max rel", float(rel.max()))
+        assert rel.max() <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_greeks_equal_single_calls(precision):
+    batch = _mixed()
+    _say("batch greeks", precision)
+    br = rq.price_batch(batch, precision=precision, greeks=True)
+    for k, ins in enumerate(batch):
+        if ins.kind == "lmm":
+            r = rq.price_caplets(ins.model, ins.N, ins.M, ins.seed, m_offset=ins.m_offset, flags=ins.flags,
+                                 precision=precision, greeks=True)
+        else:
+            r = rq.price_mbs(ins.model, ins.N, ins.M, ins.seed, m_offset=ins.m_offset, flags=ins.flags,
+                             precision=precision, greeks=True)
+        for a, b in ((br.results[k].theta, r.theta), (br.results[k].greeks.theta, r.greeks.theta)):
+            a, b = _np(a), _np(b)
+            scale = np.abs(b).max(axis=1, keepdims=True) + 1e-300
+            assert (np.abs(a - b) <= 1e-13 * scale).all(), (k, float((np.abs(a - b) / scale).max()))
+
+
+def test_batch_invariant_to_launch_shape():
+    batch = _mixed()
+    _say("batch launch shapes")
+    ref = rq.price_batch(batch, precision="fp32", greeks=True, tuning=(1, 0, rq.ORDER_COST))
+    for tu in ((4, 2, rq.ORDER_GIVEN), (8, 1, rq.ORDER_COST), (2, 3, rq.ORDER_GIVEN)):
+        got = rq.price_batch(batch, precision="fp32", greeks=True, tuning=tu)
+        for k in range(len(batch)):
+            for a, b in ((got.results[k].theta, ref.results[k].theta),
+                         (got.results[k].greeks.theta, ref.results[k].greeks.theta),
+                         (got.results[k].se, ref.results[k].se)):
+                assert np.array_equal(_np(a).view(np.uint64), _np(b).view(np.uint64)), (tu, k)
+
+
+def test_batch_timestamps_bracket_every_instrument():
+    batch = _mixed()
+    br = rq.price_batch(batch, precision="fp32", timestamps=True)
+    tf, tl = _np(br.t_first).view(np.uint64), _np(br.t_last).view(np.uint64)
+    assert (tf != np.uint64(0xFFFFFFFFFFFFFFFF)).all() and (tl > 0).all()
+    assert (tf <= tl).all()
+    hz = rq.realtime_hz()
+    span_s = float((tl.max() - tf.min())) / hz
+    _say("batch span s", span_s, "counter Hz", hz)
+    assert 0 < span_s < 60
+
+
+def test_autotune_picks_a_candidate_and_keeps_results():
+    batch = _mixed()
+    _say("autotune")
+    (chunk, per_cu, order), ms = rq.autotune_batch(batch, precision="fp32", greeks=True)
+    assert chunk in (1, 2, 4, 8) and per_cu >= 1 and order in (rq.ORDER_COST, rq.ORDER_GIVEN) and ms > 0
+    a = rq.price_batch(batch, precision="fp32", greeks=True, tuning=(chunk, per_cu, order))
+    b = rq.price_batch(batch, precision="fp32", greeks=True)
+    for k in range(len(batch)):
+        assert np.array_equal(_np(a.results[k].theta), _np(b.results[k].theta))
+
+
+def test_batch_of_the_256_instrument_workload_scaled_down():
+    # the seeded 256-instrument list with N capped at 2^10 and M at 4 (the
+    # shapes otherwise unchanged): every result finite, sampled instruments
+    # equal to their single calls
+    full = I.cfg5()
+    batch = [Ins(c.kind, c.model, min(c.N, 1 << 10), min(c.M, 4), c.seed) for c in full]
+    _say("cfg5 scaled", len(batch))
+    br = rq.price_batch(batch, precision="fp32", greeks=True)
+    for k in range(len(batch)):
+        assert np.isfinite(_np(br.results[k].theta)).all() and np.isfinite(_np(br.results[k].greeks.theta)).all()
+    for k in (0, 1, 77, 128, 255):
+        ins = batch[k]
+        f = rq.price_caplets if ins.kind == "lmm" else rq.price_mbs
+        r = f(ins.model, ins.N, ins.M, ins.seed, precision="fp32", greeks=True)
+        assert np.allclose(_np(br.results[k].theta), _np(r.theta), rtol=1e-13, atol=0), k
+        assert np.allclose(_np(br.results[k].greeks.theta), _np(r.greeks.theta), rtol=1e-13,
+                           atol=1e-13 * np.abs(_np(r.greeks.theta)).max()), k
+
+
+def test_batch_rejects_bad_instrument_before_launch():
+    bad = I.small_lmm(4, 2)
+    bad.L0 = bad.L0.copy()
+    bad.L0[2] = -1.0
+    batch = [Ins("mbs", I.mbs_paper(12), 64, 1, 1), Ins("lmm", bad, 64, 1, 1)]
+    with pytest.raises(rq.RqError, match="instrument 1"):
+        rq.price_batch(batch)
