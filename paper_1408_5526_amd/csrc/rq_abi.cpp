@@ -348,8 +348,10 @@ rq_status check_lmm(const rq_lmm_model *m)
     return RQ_OK;
 }
 
-// Table rows: n_fwd rounded up to whole groups.
-int lmm_rows(int nf) { return (nf + rq::kGrp - 1) / rq::kGrp * rq::kGrp; }
+// Table rows: every table has kMaxFwd rows, the rows beyond n_fwd zero (the
+// kernels read up to their compile-time capacity without per-forward
+// guards).
+int lmm_rows(int) { return rq::kMaxFwd; }
 
 // Forward tables: FP64 rows then FP32 rows (layout in rq_internal.h).
 std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
@@ -376,6 +378,7 @@ std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
         const double K = m->strike[n - 1];
         r[8] = std::isnan(K) ? 0.0 : K;
         r[9] = std::isnan(K) ? 0.0 : 1.0;
+        r[10] = 1.0 / (m->L0[n] * 0.69314718055994530942);
         q[6] = (float)(log2e * r[6]);
         q[7] = (float)std::log2(m->delta * m->L0[n]);
     }

@@ -261,13 +261,24 @@ __device__ __forceinline__ double wave_sum(double v)
 // summation tree is fixed, so the result is deterministic.
 __device__ __forceinline__ double wave_sum16(double (&v)[16], int lane)
 {
+    // The per-lane choice between v[q] and v[q+h] is a bitwise select under
+    // a mask the optimizer cannot see through: written as a conditional it
+    // becomes a lane-dependent index into the array, lowered to a compare
+    // per element whose masks end up in (spilled) scalar registers.
+    auto pick = [](uint32_t m, double a, double b) -> double {
+        const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+        const uint32_t lo = ((uint32_t)ua & m) | ((uint32_t)ub & ~m);
+        const uint32_t hi = ((uint32_t)(ua >> 32) & m) | ((uint32_t)(ub >> 32) & ~m);
+        return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    };
 #pragma unroll
     for (int h = 8, b = 32; h >= 1; h >>= 1, b >>= 1) {
-        const bool up = (lane & b) != 0;
+        uint32_t up = (lane & b) ? ~0u : 0u;
+        asm volatile("" : "+v"(up));
 #pragma unroll
         for (int q = 0; q < h; ++q) {
-            const double send = up ? v[q] : v[q + h];
-            const double keep = up ? v[q + h] : v[q];
+            const double send = pick(up, v[q], v[q + h]);
+            const double keep = pick(up, v[q + h], v[q]);
             v[q] = keep + __shfl_xor(send, b, kWave);
         }
     }
@@ -291,6 +302,22 @@ template <typename T>
 __device__ __forceinline__ cptr<T> as_const(const void *p)
 {
     return (cptr<T>)p;
+}
+
+// A wave-uniform value the compiler must treat as new at this point: loads
+// and comparisons derived from it are not hoisted above it (out of a
+// persistent loop), where they would stay live in scalar registers.
+__device__ __forceinline__ int opaque_u(int v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ cptr<T> opaque_u(cptr<T> p)
+{
+    uint64_t u = (uint64_t)p;
+    asm volatile("" : "+s"(u));
+    return (cptr<T>)u;
 }
 
 // A wave-uniform struct read through the constant address space (scalar

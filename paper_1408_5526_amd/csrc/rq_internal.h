@@ -84,12 +84,13 @@ struct SetupArgs {
 //   [7]    L_n(0)
 //   [8]    K_n (0 when there is no caplet)
 //   [9]    1 if forward n carries a caplet, else 0
+//   [10]   1 / (L_n(0) ln 2)
 // followed by the FP32 rows, kRow32 floats per forward, log2 units:
 //   [0..2] log2(e) a_n
 //   [3..5] delta a_n
 //   [6]    log2(e) c_n
 //   [7]    log2(delta L_n(0))
-// Both tables are padded with zero rows to a multiple of kGrp forwards.
+// Every table has kMaxFwd rows; the rows beyond n_fwd are zero.
 constexpr int kFwdRow = 12;
 constexpr int kRow32 = 8;
 constexpr int kGrp = 4;   // forwards per branch-free group of the LIBOR kernel

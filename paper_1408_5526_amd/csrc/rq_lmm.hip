@@ -40,7 +40,7 @@ namespace rq {
 
 
 template <int NFC, int D, typename T, bool PERM>
-__global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void lmm_kernel(LmmArgs a)
 {
     static_assert(NFC % 16 == 0, "capacity must be a multiple of 16");
     constexpr bool kF32 = sizeof(T) == 4;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a)
     // state: FP32 X_n = log2(L_n / L_n(0)); FP64 L_n
     T X[NFC];
 #pragma unroll
-    for (int n = 0; n < NFC; ++n) X[n] = kF32 ? T(0) : (n < nf ? T(r64(n, 7)) : T(0));
+    for (int n = 0; n < NFC; ++n) X[n] = kF32 ? T(0) : T(r64(n, 7));   // rows beyond n_fwd are 0
 
     const T sqd = (T)a.sqrt_delta;
     const double delta = a.delta;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a)
 #pragma unroll
         for (int gq = 0; gq < NFC / kGrp; ++gq) {
             const int n0 = gq * kGrp;
-            if (n0 + kGrp > k && n0 < nf) {
+            if ((unsigned)(n0 + kGrp - 1 - k) < (unsigned)(nf + kGrp - 1 - k)) {   // k - 3 <= n0 < nf
 #pragma unroll
                 for (int u = 0; u < kGrp; ++u) {
                     // wave-uniform 0/1, formed as bits so that it stays scalar
@@ -149,20 +149,17 @@ __global__ __launch_bounds__(kBlock) void lmm_kernel(LmmArgs a)
             double P[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
+                // rows beyond n_fwd are 0 (no numeraire factor, no payoff);
+                // the caplet flag multiplies the payoff
                 const int n = c * 16 + q;
-                double pay = 0.0;
-                if (n < nf) {
-                    const double Lf = kF32 ? r64(n, 7) * exp2((double)X[n]) : (double)X[n];
-                    const double onep = 1.0 + delta * Lf;
-                    if (r64(n, 9) != 0.0) {
-                        const double ex = Lf - r64(n, 8);
-                        pay = ex > 0.0 ? delta * ex / (num * onep) : 0.0;
-                    }
-                    num *= onep;
-                    pay = active ? pay : 0.0;
-                    book += pay;
-                    if (pp) pp[n] = pay;
-                }
+                const double Lf = kF32 ? r64(n, 7) * exp2((double)X[n]) : (double)X[n];
+                const double onep = 1.0 + delta * Lf;
+                const double ex = Lf - r64(n, 8);
+                double pay = ex > 0.0 ? r64(n, 9) * (delta * ex / (num * onep)) : 0.0;
+                num *= onep;
+                pay = active ? pay : 0.0;
+                book += pay;
+                if (pp) pp[n < nf ? n : nf] = pay;   // beyond n_fwd: 0 into the book slot, rewritten below
                 P[q] = pay;
             }
             const double s = wave_sum16(P, lane);

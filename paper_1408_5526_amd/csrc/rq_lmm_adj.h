@@ -60,13 +60,14 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     constexpr bool kF32 = sizeof(T) == 4;
     constexpr T kLn2 = T(0.69314718055994530942);
     const int lane = threadIdx.x;
-    const cptr<double> fwd = as_const<double>(a.fwd);
-    const cptr<T> tab = as_const<T>(a.adj);
-    const int nf = a.n_fwd;
+    // per task: keeps the forward count, the tables and all that derives
+    // from them out of scalar registers between tasks
+    const cptr<double> fwd = opaque_u(as_const<double>(a.fwd));
+    const cptr<T> tab = opaque_u(as_const<T>(a.adj));
+    const int nf = opaque_u(a.n_fwd);
     const double delta = a.delta;
     const T sqd = (T)a.sqrt_delta;
 
-    auto r64 = [&](int n, int c) -> double { return fwd[n * kFwdRow + c]; };
     auto G = [&](T s) -> T { return adj_rcp<T>(T(1) + adj_exp2<T>(-s)); };
 
     const int64_t i = (int64_t)blk * kWave + lane;
@@ -109,7 +110,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll
             for (int gq = 0; gq < NFC / kGrp; ++gq) {
                 const int n0 = gq * kGrp;
-                if (n0 + kGrp > k && n0 < nf) {
+                if ((unsigned)(n0 + kGrp - 1 - k) < (unsigned)(nf + kGrp - 1 - k)) {   // k - 3 <= n0 < nf
 #pragma unroll
                     for (int u = 0; u < kGrp; ++u)
                         body(n0 + u, __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
@@ -139,19 +140,30 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     double *out = a.partial + (size_t)task * a.n_out;
     double *gout = GREEKS ? a.partial_g + (size_t)task * a.n_g : nullptr;
     double book = 0.0;
+    // Rows beyond n_fwd are zero (L_n(0) = 0: no numeraire factor, no
+    // payoff, no adjoint), so the loops need no per-forward guard; the
+    // caplet flag multiplies the payoff.  Each pass re-reads the table
+    // through a fresh pointer so that no row value stays live in scalar
+    // registers from one pass to the next.
     if constexpr (GREEKS) {
+        const cptr<double> f1 = opaque_u(fwd);
         double num = a.num0;
 #pragma unroll
-        for (int n = 0; n < NFC; ++n) {
-            if (n < nf) {
-                const double Lf = r64(n, 7) * exp2((double)X[n]);
-                num *= 1.0 + delta * Lf;
-                const double ex = Lf - r64(n, 8);
-                if (r64(n, 9) != 0.0 && ex > 0.0) book += delta * ex / num;
+        for (int c = 0; c < NFC / 16; ++c) {
+            if (c * 16 < nf) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int n = c * 16 + q;
+                    const double Lf = f1[n * kFwdRow + 7] * exp2((double)X[n]);
+                    num *= 1.0 + delta * Lf;
+                    const double ex = Lf - f1[n * kFwdRow + 8];
+                    book += ex > 0.0 ? f1[n * kFwdRow + 9] * (delta * ex / num) : 0.0;
+                }
             }
         }
     }
     {
+        const cptr<double> f2 = opaque_u(fwd);
         double num = a.num0;
         double before = 0.0;   // sum_{j<n} P_j
 #pragma unroll
@@ -161,24 +173,22 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int n = c * 16 + q;
-                    double Pn = 0.0;
-                    if (n < nf) {
-                        const double Lf = r64(n, 7) * exp2((double)X[n]);
-                        const double onep = 1.0 + delta * Lf;
-                        num *= onep;
-                        const double ex = Lf - r64(n, 8);
-                        const bool itm = r64(n, 9) != 0.0 && ex > 0.0;
-                        if (itm) Pn = delta * ex / num;
-                        if constexpr (GREEKS) {
-                            double dL = -delta / onep * (book - before);
-                            if (itm) dL += delta / num;
-                            vbar[n][lane] = (T)(dL * Lf * 0.69314718055994530942);
-                            before += Pn;
-                        } else {
-                            book += Pn;
-                        }
-                        if (pp) pp[n] = Pn;
+                    const double Lf = f2[n * kFwdRow + 7] * exp2((double)X[n]);
+                    const double onep = 1.0 + delta * Lf;
+                    num *= onep;
+                    const double rn = delta / num;
+                    const double ex = Lf - f2[n * kFwdRow + 8];
+                    const double flag = f2[n * kFwdRow + 9];
+                    const double Pn = ex > 0.0 ? flag * (ex * rn) : 0.0;
+                    if constexpr (GREEKS) {
+                        double dL = -delta / onep * (book - before);
+                        if (ex > 0.0) dL += flag * rn;
+                        vbar[n][lane] = (T)(dL * Lf * 0.69314718055994530942);
+                        before += Pn;
+                    } else {
+                        book += Pn;
                     }
+                    if (pp) pp[n < nf ? n : nf] = Pn;   // beyond n_fwd: 0 into the book slot, rewritten below
                     V[q] = Pn * act;
                 }
                 const double sv = wave_sum16(V, lane);
@@ -200,8 +210,8 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 
     // ---- reverse sweep ----
 #pragma unroll
-    for (int n = 0; n < NFC; ++n) {
-        Xb[n] = n < nf ? vbar[n][lane] : T(0);
+    for (int n = 0; n < NFC; ++n) {   // rows beyond n_fwd hold 0
+        Xb[n] = vbar[n][lane];
         vbar[n][lane] = T(0);
     }
     T wn[D];
@@ -250,7 +260,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll
             for (int gq = NFC / kGrp - 1; gq >= 0; --gq) {
                 const int n0 = gq * kGrp;
-                if (n0 + kGrp > k && n0 < nf) {
+                if ((unsigned)(n0 + kGrp - 1 - k) < (unsigned)(nf + kGrp - 1 - k)) {   // k - 3 <= n0 < nf
 #pragma unroll
                     for (int u = kGrp - 1; u >= 0; --u)
                         body(n0 + u, __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
@@ -265,6 +275,9 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     }
 
     // ---- Greeks [2 nf + 1]: deltas, spot delta (above), vegas ----
+    // dbook/dL_n(0) = Xbar_n / (L_n(0) ln 2): row entry 10 is 1/(L_n(0) ln 2),
+    // 0 beyond n_fwd, where Xbar and the vega rows are 0 as well
+    const cptr<double> f3 = opaque_u(fwd);
 #pragma unroll
     for (int c = 0; c < NFC / 16; ++c) {
         if (c * 16 < nf) {
@@ -274,15 +287,12 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int n = c * 16 + q;
-                V[q] = n < nf ? (double)Xb[n] / (r64(n, 7) * 0.69314718055994530942) * act : 0.0;
+                V[q] = (double)Xb[n] * f3[n * kFwdRow + 10] * act;
             }
             double s = wave_sum16(V, lane);
             if (wr) gout[o] = s;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int n = c * 16 + q;
-                V[q] = n < nf ? (double)vbar[n][lane] * act : 0.0;
-            }
+            for (int q = 0; q < 16; ++q) V[q] = (double)vbar[c * 16 + q][lane] * act;
             s = wave_sum16(V, lane);
             if (wr) gout[nf + 1 + o] = s;
         }
