@@ -27,6 +27,7 @@ _lib = None
 START_RANDOM = 0
 START_ZERO = 1
 PERM_RANDOM = 2
+MC_PHILOX = 8
 
 _dp = C.POINTER(C.c_double)
 _u64p = C.POINTER(C.c_uint64)
@@ -56,6 +57,10 @@ def _load():
     lib.orc_radinv_R.argtypes = [C.c_uint64, C.c_int, _ip, C.c_uint64]
     lib.orc_point_from_R.restype = C.c_double
     lib.orc_point_from_R.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_philox4x64.restype = None
+    lib.orc_philox4x64.argtypes = [_u64p, _u64p, _u64p]
+    lib.orc_mc_point.restype = C.c_double
+    lib.orc_mc_point.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, C.c_int]
     lib.orc_ppnd16.restype = C.c_double
     lib.orc_ppnd16.argtypes = [C.c_double]
     lib.orc_ppnd16_vec.restype = None
@@ -177,13 +182,34 @@ def ppnd16(u) -> np.ndarray:
 def sequence(s: int, N: int, M: int, seed: int, flags: int = 0, m_offset: int = 0,
              gen: int = 0) -> Tuple[np.ndarray, np.ndarray]:
     """Points x[M][N][s] and integers R[M][N][s] of the random-start Halton
-    replications (gen 0: definition, gen 1: Algorithm 2)."""
+    replications (gen 0: definition, gen 1: Algorithm 2).  With
+    flags & MC_PHILOX the points are Philox4x64-10 uniforms and R is None."""
     x = np.empty((M, N, s), dtype=np.float64)
+    if flags & MC_PHILOX:
+        st = _load().orc_sequence(s, N, M, seed, flags, m_offset, gen, _d(x), None)
+        if st:
+            raise RuntimeError(f"orc_sequence status {st}")
+        return x, None
     R = np.empty((M, N, s), dtype=np.uint64)
     st = _load().orc_sequence(s, N, M, seed, flags, m_offset, gen, _d(x), R.ctypes.data_as(_u64p))
     if st:
         raise RuntimeError(f"orc_sequence status {st}")
     return x, R
+
+
+def philox4x64(ctr, key) -> Tuple[int, int, int, int]:
+    """Philox4x64-10 (Salmon et al., SC'11) of a 4-word counter under a
+    2-word key."""
+    c = (C.c_uint64 * 4)(*[int(v) for v in ctr])
+    k = (C.c_uint64 * 2)(*[int(v) for v in key])
+    o = (C.c_uint64 * 4)()
+    _load().orc_philox4x64(c, k, o)
+    return tuple(int(v) for v in o)
+
+
+def mc_point(seed: int, m_global: int, i: int, j: int) -> float:
+    """Pseudo-random coordinate j of point i of replication m_global."""
+    return float(_load().orc_mc_point(seed, m_global, i, j))
 
 
 # -- models ---------------------------------------------------------------

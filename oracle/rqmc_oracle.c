@@ -20,6 +20,9 @@
  *     Euler discretisation, taken in log form), caplet payoffs discounted
  *     by the spot numeraire (caplet section).
  *   - Caflisch MBS paths (MBS section): u_k, m_k, r_k, c_k, i_k, w_k.
+ *   - The pseudo-random comparison (the paper's Philox baseline): the same
+ *     paths driven by Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11)
+ *     uniforms instead of Halton points.
  *   - Per-replication estimates theta_N^m, grand average RQ_{M,N}, sample
  *     standard deviation and standard error (Introduction).
  *
@@ -40,6 +43,7 @@
 
 #define ORC_START_ZERO 1
 #define ORC_PERM_RANDOM 2
+#define ORC_MC_PHILOX 8
 
 /* ------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
@@ -152,6 +156,47 @@ uint64_t orc_radinv_R(uint64_t p, int D, const int *sigma, uint64_t idx)
 double orc_point_from_R(uint64_t R, uint64_t P)
 {
     return (double)R / (double)P;
+}
+
+/* ------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC'11).  A counter (c0, c1, c2, c3) and a key (k0, k1)
+ * of 64-bit words; one round replaces the counter by
+ *   (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
+ * where hi/lo are the halves of the 128-bit product, and then adds the
+ * Weyl constants to the key; ten rounds.  Multipliers and Weyl constants
+ * are those of the publication for the 4x64 member of the family. */
+void orc_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        const unsigned __int128 p0 = (unsigned __int128)M0 * c0;
+        const unsigned __int128 p1 = (unsigned __int128)M1 * c2;
+        const uint64_t n0 = (uint64_t)(p1 >> 64) ^ c1 ^ k0;
+        const uint64_t n1 = (uint64_t)p1;
+        const uint64_t n2 = (uint64_t)(p0 >> 64) ^ c3 ^ k1;
+        const uint64_t n3 = (uint64_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Pseudo-random coordinate j of point i of replication m_global:
+ * word (j mod 4) of Philox4x64-10 at counter (j / 4, i, 0, 0) under key
+ * (seed, m_global), mapped to ((x >> 11) + 1/2) 2^-53, which lies in (0, 1)
+ * and is exact in FP64. */
+double orc_mc_point(uint64_t seed, uint64_t m_global, uint64_t i, int j)
+{
+    const uint64_t ctr[4] = {(uint64_t)j >> 2, i, 0, 0};
+    const uint64_t key[2] = {seed, m_global};
+    uint64_t w[4];
+    orc_philox4x64(ctr, key, w);
+    return ((double)(w[j & 3] >> 11) + 0.5) * 0x1p-53;
 }
 
 /* ------------------------------------------------------------------ */
@@ -418,6 +463,16 @@ int orc_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t m_of
                  double *out_x, uint64_t *out_R)
 {
     if (s < 1 || N < 1 || M < 1 || s > 4096) return ORC_EINVAL;
+    if (flags & ORC_MC_PHILOX) {
+        if ((flags & (ORC_START_ZERO | ORC_PERM_RANDOM)) || out_R) return ORC_EINVAL;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int m = 0; m < M; ++m)
+            for (int64_t i = 0; i < N; ++i)
+                for (int j = 0; j < s; ++j)
+                    out_x[((size_t)m * (size_t)N + (size_t)i) * (size_t)s + (size_t)j] =
+                        orc_mc_point(seed, (uint64_t)(m_offset + m), (uint64_t)i, j);
+        return ORC_OK;
+    }
     orc_base *bs = (orc_base *)calloc((size_t)s, sizeof(orc_base));
     int st = orc_bases(s, seed, flags, bs);
     if (!st) st = orc_check_N(s, N, bs);
@@ -457,9 +512,11 @@ static int orc_price(int s, int n_out, orc_path_fn path, const void *ctx, int64_
                      uint64_t seed, int64_t m_offset, int flags, double *theta, double *per_path)
 {
     if (s < 1 || N < 1 || M < 1 || s > 4096 || n_out < 1) return ORC_EINVAL;
+    const int mc = (flags & ORC_MC_PHILOX) != 0;
+    if (mc && (flags & (ORC_START_ZERO | ORC_PERM_RANDOM))) return ORC_EINVAL;
     orc_base *bs = (orc_base *)calloc((size_t)s, sizeof(orc_base));
-    int st = orc_bases(s, seed, flags, bs);
-    if (!st) st = orc_check_N(s, N, bs);
+    int st = mc ? ORC_OK : orc_bases(s, seed, flags, bs);
+    if (!st && !mc) st = orc_check_N(s, N, bs);
     if (st) { orc_bases_free(s, bs); free(bs); return st; }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
@@ -468,16 +525,21 @@ static int orc_price(int s, int n_out, orc_path_fn path, const void *ctx, int64_
         double *z = (double *)malloc(sizeof(double) * (size_t)s);
         double *f = (double *)malloc(sizeof(double) * (size_t)n_out);
         orc_acc *acc = (orc_acc *)calloc((size_t)n_out, sizeof(orc_acc));
-        for (int j = 0; j < s; ++j) {
+        for (int j = 0; j < s && !mc; ++j) {
             uint64_t n;
             if (orc_start(seed, (uint64_t)(m_offset + m), j, bs[j].P, flags, &n)) err |= 1;
             orc_alg2_init(&g[j], bs[j].p, bs[j].D, bs[j].sigma, n);
         }
         for (int64_t i = 0; i < N; ++i) {
             for (int j = 0; j < s; ++j) {
-                double x = orc_point_from_R(orc_alg2_R(&g[j]), bs[j].P);
+                double x;
+                if (mc) {
+                    x = orc_mc_point(seed, (uint64_t)(m_offset + m), (uint64_t)i, j);
+                } else {
+                    x = orc_point_from_R(orc_alg2_R(&g[j]), bs[j].P);
+                    orc_alg2_next(&g[j]);
+                }
                 z[j] = orc_ppnd16(x);
-                orc_alg2_next(&g[j]);
             }
             path(ctx, z, f);
             for (int o = 0; o < n_out; ++o) orc_acc_add(&acc[o], f[o]);
