@@ -45,7 +45,7 @@ PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 
 
 ADJ_SOURCES = ("rq_lmm_adj.h", "rq_lmm_adj32.hip", "rq_device.h", "rq_internal.h")
-PRICE_SOURCES = ("rq_lmm.hip", "rq_device.h", "rq_internal.h")
+PRICE_SOURCES = ("rq_lmm.h", "rq_lmm.hip", "rq_device.h", "rq_internal.h")
 
 
 def _kernel_source_hash(names) -> str:
@@ -218,6 +218,14 @@ def main(argv=None):
         "vega_s40": gm[81 + 39].item(), "vega_s40_se": gse[81 + 39].item(),
         "delta_spot": gm[80].item(),
     }
+    # the paper's comparison: the same kernels on Philox pseudo-random points
+    ms_mc, kms_mc, res_mc = _time_steps(
+        lambda: rq.price_caplets(model, N, M, seed, flags=rq.MC_PHILOX, precision="fp32", device=dev, ws=ws),
+        args.steps, args.warmup)
+    out_extra["mc_philox_fp32"] = {
+        "paths_per_s": N * M / (ms_mc / 1e3), "kernel_ms": kms_mc,
+        "book_rq": res_mc.mean[-1].item(), "book_se": res_mc.se[-1].item(),
+        "se_ratio_mc_over_rqmc": res_mc.se[-1].item() / res.se[-1].item()}
     out_extra["prices_only_fp32"] = {
         "paths_per_s": N * M / (ms / 1e3), "ms_per_step": ms, "kernel_ms": kms,
         "achieved_tflops": FLOPS_PER_PATH_LMM80 * N * M / (kms / 1e3) / 1e12,

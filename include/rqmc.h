@@ -32,6 +32,13 @@
  *                   nonzero digit stay unpermuted.
  *   RQ_OUT_DIGITS   rq_sequence only: emit the exact integers R (uint64)
  *                   instead of the FP64 points.
+ *   RQ_MC_PHILOX    pseudo-random points instead of Halton (the paper's
+ *                   Philox comparison): coordinate j of point i of
+ *                   replication m_global is word (j mod 4) of Philox4x64-10
+ *                   (Salmon, Moraes, Dror & Shaw, SC'11) at counter
+ *                   (j/4, i, 0, 0) under key (seed, m_global), mapped to
+ *                   ((x >> 11) + 1/2) 2^-53.  Excludes the three flags above;
+ *                   N is not limited by P_j.
  * Normals.  Dimension j of a path maps to z = Phi^{-1}(x) (Wichura's
  *   AS241 in FP64; the FP32 form folds r = min(x, 1-x) in FP64 first).
  * Memory.  Every pointer named "device" is a device (HBM) address on the
@@ -76,7 +83,8 @@ enum {
     RQ_START_RANDOM = 0,
     RQ_START_ZERO = 1,
     RQ_PERM_RANDOM = 2,
-    RQ_OUT_DIGITS = 4
+    RQ_OUT_DIGITS = 4,
+    RQ_MC_PHILOX = 8
 };
 
 /* Limits of this build. */

@@ -247,13 +247,16 @@ rq_status check_common(int s, int64_t N, int M, int flags, int64_t m_offset, Geo
     if (N < 1) return fail(RQ_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
     if (M < 1) return fail(RQ_EINVAL, "M must be >= 1 (got %d)", M);
     if (m_offset < 0) return fail(RQ_EINVAL, "m_offset must be >= 0");
-    if (flags & ~(RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS))
+    if (flags & ~(RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS | RQ_MC_PHILOX))
         return fail(RQ_EINVAL, "unknown flag bits 0x%x", flags);
+    const bool mc = (flags & RQ_MC_PHILOX) != 0;
+    if (mc && (flags & (RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS)))
+        return fail(RQ_EINVAL, "RQ_MC_PHILOX excludes RQ_START_ZERO, RQ_PERM_RANDOM and RQ_OUT_DIGITS");
     if (s > RQ_MAX_DIM) return fail(RQ_ERANGE, "s = %d beyond the %d supported bases", s, RQ_MAX_DIM);
     if (m_offset + (int64_t)M > RQ_MAX_REPLICATION)
         return fail(RQ_ERANGE, "m_offset + M beyond 2^40");
     const auto &pr = primes();
-    for (int j = 0; j < s; ++j) {
+    for (int j = 0; j < s && !mc; ++j) {
         const uint64_t P = ipow(pr[j], digits_D(pr[j]));
         if ((uint64_t)N > P)
             return fail(RQ_ERANGE, "N = %lld exceeds P_%d = %llu (base %u)", (long long)N, j,
@@ -294,11 +297,12 @@ rq_status stage_and_setup(const PointTables &pt, const std::vector<uint8_t> &mod
     a.n_seg = g.n_seg;
     a.S = g.S;
     a.flags = flags;
-    RQ_HIP(rq::launch_setup(a, st));
+    if (!(flags & RQ_MC_PHILOX)) RQ_HIP(rq::launch_setup(a, st));   // pseudo-random points need no starts
     return RQ_OK;
 }
 
-rq::SeqGeom seq_geom(const Layout &L, const Geometry &g, uint8_t *ws, int s, int M, int64_t N, int flags)
+rq::SeqGeom seq_geom(const Layout &L, const Geometry &g, uint8_t *ws, int s, int M, int64_t N, int flags,
+                     uint64_t seed, int64_t m_offset)
 {
     rq::SeqGeom sg;
     sg.base = reinterpret_cast<const BaseEnt *>(ws + L.base);
@@ -308,6 +312,9 @@ rq::SeqGeom seq_geom(const Layout &L, const Geometry &g, uint8_t *ws, int s, int
     sg.M = M;
     sg.n_seg = g.n_seg;
     sg.perm_on = (flags & RQ_PERM_RANDOM) ? 1 : 0;
+    sg.mc = (flags & RQ_MC_PHILOX) ? 1 : 0;
+    sg.seed = seed;
+    sg.m_offset = m_offset;
     sg.N = N;
     sg.S = g.S;
     sg.log2S = g.log2S;
@@ -587,7 +594,7 @@ rq_status plan_batch(const rq_instrument *inst, int n_inst, rq_precision prec, b
         } else {
             p.model_bytes = 2 * (size_t)(p.months + 1) * sizeof(double);
         }
-        p.setup_units = (int64_t)p.M * p.g.n_seg * p.s;
+        p.setup_units = (p.flags & RQ_MC_PHILOX) ? 0 : (int64_t)p.M * p.g.n_seg * p.s;
     }
     bp.order.resize(n_inst);
     for (int k = 0; k < n_inst; ++k) bp.order[k] = k;
@@ -721,7 +728,7 @@ rq_status run_batch(const rq_instrument *inst, int n_inst, rq_precision prec, bo
         L.model = p.o_model;
         L.starts = p.o_starts;
         L.partial = p.o_part;
-        const rq::SeqGeom sg = seq_geom(L, p.g, w, p.s, p.M, p.N, p.flags);
+        const rq::SeqGeom sg = seq_geom(L, p.g, w, p.s, p.M, p.N, p.flags, p.seed, p.m_offset);
         rq::BatchInst &d = bi[e];
         std::memset(&d, 0, sizeof d);
         d.kind = p.kind;
@@ -928,7 +935,7 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
     if ((stt = stage_and_setup(pt, {}, L, g, s, M, seed, m_offset, flags, w, st))) return stt;
     {
         TimedRegion tr(st);
-        RQ_HIP(rq::launch_sequence(seq_geom(L, g, w, s, M, N, flags), flags, out, st));
+        RQ_HIP(rq::launch_sequence(seq_geom(L, g, w, s, M, N, flags, seed, m_offset), flags, out, st));
     }
     return RQ_OK;
 }
@@ -1008,7 +1015,7 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     uint8_t *w = (uint8_t *)ws;
     if ((stt = stage_and_setup(pt, tab, L, g, s, M, seed, m_offset, flags, w, st))) return stt;
     rq::LmmArgs a;
-    a.g = seq_geom(L, g, w, s, M, N, flags);
+    a.g = seq_geom(L, g, w, s, M, N, flags, seed, m_offset);
     a.fwd = reinterpret_cast<const double *>(w + L.model);
     a.fwd32 = reinterpret_cast<const float *>(w + L.model + (size_t)lmm_rows(model->n_fwd) * rq::kFwdRow * sizeof(double));
     a.adj = greeks ? (const void *)(w + L.model + adj_off) : nullptr;
@@ -1071,7 +1078,7 @@ rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t s
     uint8_t *w = (uint8_t *)ws;
     if ((stt = stage_and_setup(pt, tab, L, g, s, M, seed, m_offset, flags, w, st))) return stt;
     rq::MbsArgs a;
-    a.g = seq_geom(L, g, w, s, M, N, flags);
+    a.g = seq_geom(L, g, w, s, M, N, flags, seed, m_offset);
     a.ck = reinterpret_cast<const double *>(w + L.model);
     a.partial = reinterpret_cast<double *>(w + L.partial);
     a.per_path = per_path;

@@ -52,10 +52,14 @@ void batch_kernel(BatchArgs b)
                 const LmmArgs a = load_uniform<LmmArgs>(&b.inst[lo].lmm);
                 const int m = (int)(local / a.n_blk);
                 const int blk = (int)(local - (int64_t)m * a.n_blk);
-                switch (inst[lo].n_factors) {
-                case 1: lmm_task<kMaxFwd, 1, T, GREEKS>(a, m, blk, local, wt, vbar); break;
-                case 2: lmm_task<kMaxFwd, 2, T, GREEKS>(a, m, blk, local, wt, vbar); break;
-                default: lmm_task<kMaxFwd, 3, T, GREEKS>(a, m, blk, local, wt, vbar); break;
+                const int sel = inst[lo].n_factors * 2 + (a.g.mc ? 1 : 0);
+                switch (sel) {
+                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false>(a, m, blk, local, wt, vbar); break;
+                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true>(a, m, blk, local, wt, vbar); break;
+                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false>(a, m, blk, local, wt, vbar); break;
+                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true>(a, m, blk, local, wt, vbar); break;
+                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true>(a, m, blk, local, wt, vbar); break;
+                default: lmm_task<kMaxFwd, 3, T, GREEKS, false>(a, m, blk, local, wt, vbar); break;
                 }
             } else {
                 const MbsArgs a = load_uniform<MbsArgs>(&b.inst[lo].mbs);

@@ -304,6 +304,56 @@ __device__ __forceinline__ cptr<T> as_const(const void *p)
     return (cptr<T>)p;
 }
 
+// ---------------------------------------------------------------------------
+// Pseudo-random points (the comparison baseline): Philox4x64-10 (Salmon,
+// Moraes, Dror & Shaw, SC'11).  A round maps the counter (c0, c1, c2, c3)
+// under the key (k0, k1) to (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1,
+// lo(M0 c0)), hi/lo the halves of the 128-bit product, then adds the Weyl
+// constants to the key; ten rounds.  Coordinate j of point i of replication
+// m_global is word (j mod 4) of the block at counter (j / 4, i, 0, 0) under
+// key (seed, m_global), mapped to ((x >> 11) + 1/2) 2^-53 in (0, 1).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t (&c)[4], uint64_t k0, uint64_t k1)
+{
+    constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(kM0, c[0]), lo0 = kM0 * c[0];
+        const uint64_t hi1 = __umul64hi(kM1, c[2]), lo1 = kM1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+}
+
+__device__ __forceinline__ double u53(uint64_t x) { return ((double)(x >> 11) + 0.5) * 0x1p-53; }
+
+// The pseudo-random coordinates of one path, one Philox block (four
+// coordinates) at a time; j must be wave-uniform.
+struct McPath {
+    uint64_t w[4];
+    int blk = -1;
+    __device__ __forceinline__ double point(uint64_t seed, uint64_t m_global, uint64_t i, int j)
+    {
+        const int b = j >> 2;
+        if (b != blk) {
+            uint64_t c[4] = {(uint64_t)b, i, 0ull, 0ull};
+            philox4x64_10(c, seed, m_global);
+            w[0] = c[0];
+            w[1] = c[1];
+            w[2] = c[2];
+            w[3] = c[3];
+            blk = b;
+        }
+        const int q = j & 3;
+        return u53(q == 0 ? w[0] : q == 1 ? w[1] : q == 2 ? w[2] : w[3]);
+    }
+};
+
 // A wave-uniform value the compiler must treat as new at this point: loads
 // and comparisons derived from it are not hoisted above it (out of a
 // persistent loop), where they would stay live in scalar registers.

@@ -51,6 +51,7 @@ constexpr int kWave = 64;
 constexpr int kStartZero = 1;
 constexpr int kPermRandom = 2;
 constexpr int kOutDigits = 4;
+constexpr int kMcPhilox = 8;
 
 // Arguments common to every kernel that generates points.
 struct SeqGeom {
@@ -61,6 +62,9 @@ struct SeqGeom {
     int M;
     int n_seg;
     int perm_on;
+    int mc;                  // 1: Philox4x64-10 pseudo-random points instead of Halton
+    uint64_t seed;           // MC key word 0
+    int64_t m_offset;        // MC key word 1 = m_offset + m
     int64_t N;
     int64_t S;               // segment length (power of two)
     int log2S;

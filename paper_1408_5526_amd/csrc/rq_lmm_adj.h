@@ -50,9 +50,11 @@ template <> __device__ __forceinline__ double adj_rcp<double>(double x) { return
 
 // One task: the 64 paths of block `blk` of replication m (task = m n_blk + blk
 // indexes the partial rows).  GREEKS = false runs the forward pass and the
-// payoffs only (the batch kernel's pricing form).  wt is the lane's entry of
+// payoffs only (the batch kernel's pricing form).  MC draws the path's
+// uniforms from Philox instead of the Halton replication (a separate
+// instantiation, so the Halton form carries no pseudo-random code).  wt is the lane's entry of
 // the block's stored-w slot; vbar the block's LDS rows.
-template <int NFC, int D, typename T, bool GREEKS>
+template <int NFC, int D, typename T, bool GREEKS, bool MC>
 __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64_t task, T *__restrict__ wt,
                                          T (&vbar)[NFC][kWave])
 {
@@ -81,15 +83,21 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     for (int n = 0; n < NFC; ++n) X[n] = T(0);
 
     // ---- forward pass ----
+    McPath mc;
 #pragma unroll 1
     for (int k = 0; k < nf; ++k) {
         T w[D];
 #pragma unroll
         for (int f = 0; f < D; ++f) {
             const int j = k * D + f;
-            const PointCtx c = load_base(a.g.base, j);
-            const double x = a.g.perm_on ? radinv_x<true, !kF32>(c, st + j, t, a.g.perm)
-                                         : radinv_x<false, !kF32>(c, st + j, t, a.g.perm);
+            double x;
+            if constexpr (MC) {
+                x = mc.point(a.g.seed, (uint64_t)(a.g.m_offset + m), (uint64_t)i, j);
+            } else {
+                const PointCtx c = load_base(a.g.base, j);
+                x = a.g.perm_on ? radinv_x<true, !kF32>(c, st + j, t, a.g.perm)
+                                : radinv_x<false, !kF32>(c, st + j, t, a.g.perm);
+            }
             w[f] = sqd * inv_normal(x, T(0));
         }
         // one forward-step; on = 0 leaves a dead forward and w unchanged
@@ -301,7 +309,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 
 // FP32: the compiler is asked for two waves per SIMD (at most 256 registers);
 // the few values it then spills are outside the time loops.
-template <int NFC, int D, typename T>
+template <int NFC, int D, typename T, bool MC>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
 void lmm_adjoint_kernel(LmmArgs a)
 {
@@ -313,41 +321,43 @@ void lmm_adjoint_kernel(LmmArgs a)
     for (int64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
         const int m = (int)(task / a.n_blk);
         const int blk = (int)(task - (int64_t)m * a.n_blk);
-        lmm_task<NFC, D, T, true>(a, m, blk, task, wt, vbar);
+        lmm_task<NFC, D, T, true, MC>(a, m, blk, task, wt, vbar);
     }
 }
 
-template <int NFC, int D, typename T>
+template <int NFC, int D, typename T, bool MC>
 static hipError_t launch_adj_t(const LmmArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((lmm_adjoint_kernel<NFC, D, T>), dim3((unsigned)a.n_slots), dim3(kWave), 0, st, a);
+    hipLaunchKernelGGL((lmm_adjoint_kernel<NFC, D, T, MC>), dim3((unsigned)a.n_slots), dim3(kWave), 0, st, a);
     return hipGetLastError();
 }
 
-template <int D, typename T>
+template <int D, typename T, bool MC>
 static hipError_t launch_adj_d(const LmmArgs &a, hipStream_t st)
 {
-    if (a.n_fwd <= 16) return launch_adj_t<16, D, T>(a, st);
-    if (a.n_fwd <= 32) return launch_adj_t<32, D, T>(a, st);
-    if (a.n_fwd <= 48) return launch_adj_t<48, D, T>(a, st);
-    if (a.n_fwd <= 64) return launch_adj_t<64, D, T>(a, st);
-    return launch_adj_t<80, D, T>(a, st);
+    if (a.n_fwd <= 16) return launch_adj_t<16, D, T, MC>(a, st);
+    if (a.n_fwd <= 32) return launch_adj_t<32, D, T, MC>(a, st);
+    if (a.n_fwd <= 48) return launch_adj_t<48, D, T, MC>(a, st);
+    if (a.n_fwd <= 64) return launch_adj_t<64, D, T, MC>(a, st);
+    return launch_adj_t<80, D, T, MC>(a, st);
 }
 
-// Adjoint launch for one precision (instantiated in rq_lmm_adj32.hip and
-// rq_lmm_adj64.hip, so the two compile in parallel).
-template <typename T>
+// Adjoint launch for one precision and point generator (instantiated in
+// rq_lmm_adj{32,64}{,mc}.hip, so that the four compile in parallel).
+template <typename T, bool MC>
 static hipError_t launch_adj_prec(const LmmArgs &a, int n_factors, hipStream_t st)
 {
     switch (n_factors) {
-    case 1: return launch_adj_d<1, T>(a, st);
-    case 2: return launch_adj_d<2, T>(a, st);
-    case 3: return launch_adj_d<3, T>(a, st);
+    case 1: return launch_adj_d<1, T, MC>(a, st);
+    case 2: return launch_adj_d<2, T, MC>(a, st);
+    case 3: return launch_adj_d<3, T, MC>(a, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_lmm_adjoint_f32(const LmmArgs &a, int n_factors, hipStream_t st);
 hipError_t launch_lmm_adjoint_f64(const LmmArgs &a, int n_factors, hipStream_t st);
+hipError_t launch_lmm_adjoint_f32mc(const LmmArgs &a, int n_factors, hipStream_t st);
+hipError_t launch_lmm_adjoint_f64mc(const LmmArgs &a, int n_factors, hipStream_t st);
 
 }  // namespace rq

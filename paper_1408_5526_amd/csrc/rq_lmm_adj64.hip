@@ -1,16 +1,17 @@
-// rq_lmm_adj64.hip -- FP64 instantiations of the LIBOR adjoint kernel and the
-// precision dispatch.
+// rq_lmm_adj64.hip -- FP64 instantiations of the LIBOR adjoint kernel and the dispatch.
 #include "rq_lmm_adj.h"
 
 namespace rq {
 
 hipError_t launch_lmm_adjoint_f64(const LmmArgs &a, int n_factors, hipStream_t st)
 {
-    return launch_adj_prec<double>(a, n_factors, st);
+    return launch_adj_prec<double, false>(a, n_factors, st);
 }
 
 hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, hipStream_t st)
 {
+    if (a.g.mc)
+        return fp32 ? launch_lmm_adjoint_f32mc(a, n_factors, st) : launch_lmm_adjoint_f64mc(a, n_factors, st);
     return fp32 ? launch_lmm_adjoint_f32(a, n_factors, st) : launch_lmm_adjoint_f64(a, n_factors, st);
 }
 

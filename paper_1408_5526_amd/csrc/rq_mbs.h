@@ -23,12 +23,13 @@
 
 namespace rq {
 
-// PV (and dPV/di0 with GRAD) of the path at index t of the segment whose
-// start entries are st.
+// PV (and dPV/di0 with GRAD) of path i of replication m: Halton point at
+// index t of the segment whose start entries are st, or (MC) Philox point i.
 template <typename T, bool PERM, bool GRAD>
 __device__ __forceinline__ void mbs_path(const MbsArgs &a, const StartEnt *__restrict__ st, uint32_t t,
-                                         double &pv_out, double &dpv_out)
+                                         int m, int64_t i, double &pv_out, double &dpv_out)
 {
+    McPath mc;
     const cptr<double> ck = as_const<double>(a.ck);
     const cptr<double> dck = ck + (a.months + 1);
     const T K0 = (T)a.K0, sig = (T)a.sig, K1 = (T)a.K1, K2 = (T)a.K2, K3 = (T)a.K3, K4 = (T)a.K4;
@@ -40,8 +41,13 @@ __device__ __forceinline__ void mbs_path(const MbsArgs &a, const StartEnt *__res
 #pragma unroll 1
     for (int k = 1; k <= a.months; ++k) {
         const int j = k - 1;
-        const PointCtx c = load_base(a.g.base, j);
-        const double x = radinv_x<PERM, sizeof(T) == 8>(c, st + j, t, a.g.perm);
+        double x;
+        if (a.g.mc) {
+            x = mc.point(a.g.seed, (uint64_t)(a.g.m_offset + m), (uint64_t)i, j);
+        } else {
+            const PointCtx c = load_base(a.g.base, j);
+            x = radinv_x<PERM, sizeof(T) == 8>(c, st + j, t, a.g.perm);
+        }
         const T z = inv_normal(x, T(0));
         const double onei = 1.0 + (double)ir;
         u = u / onei;
@@ -79,8 +85,8 @@ __device__ __forceinline__ void mbs_task(const MbsArgs &a, int m, int blk, int64
     const uint32_t t = (uint32_t)(i - ((int64_t)seg << a.g.log2S));
     const StartEnt *__restrict__ st = a.g.starts + ((size_t)m * a.g.n_seg + seg) * a.g.s;
     double pv, dpv;
-    if (a.g.perm_on) mbs_path<T, true, GRAD>(a, st, t, pv, dpv);
-    else mbs_path<T, false, GRAD>(a, st, t, pv, dpv);
+    if (a.g.perm_on) mbs_path<T, true, GRAD>(a, st, t, m, i, pv, dpv);
+    else mbs_path<T, false, GRAD>(a, st, t, m, i, pv, dpv);
     pv = active ? pv : 0.0;
     dpv = active ? dpv : 0.0;
     if (a.per_path && active) a.per_path[(size_t)m * (size_t)a.g.N + (size_t)i] = pv;

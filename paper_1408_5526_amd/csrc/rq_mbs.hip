@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kBlock) void mbs_kernel(MbsArgs a)
     __shared__ double red[kBlock / kWave][2];
 
     double pv, dpv;
-    mbs_path<T, PERM, GRAD>(a, st, t, pv, dpv);
+    mbs_path<T, PERM, GRAD>(a, st, t, m, i, pv, dpv);
     pv = active ? pv : 0.0;
     dpv = active ? dpv : 0.0;
     if (a.per_path && active) a.per_path[(size_t)m * (size_t)a.g.N + (size_t)i] = pv;

@@ -42,6 +42,13 @@ __global__ __launch_bounds__(256) void sequence_kernel(SeqGeom g, int64_t tiles_
     for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
         const uint32_t ip = e / (uint32_t)g.s;
         const int j = (int)(e - ip * (uint32_t)g.s);
+        if (g.mc) {   // pseudo-random points (never with digits or permutations)
+            uint64_t c[4] = {(uint64_t)(j >> 2), (uint64_t)(i0 + ip), 0ull, 0ull};
+            philox4x64_10(c, g.seed, (uint64_t)(g.m_offset + m));
+            const int q = j & 3;
+            ((double *)out)[obase + e] = u53(q == 0 ? c[0] : q == 1 ? c[1] : q == 2 ? c[2] : c[3]);
+            continue;
+        }
         const PointCtx c = load_base(g.base, j);
         const double R = radinv_R<PERM>(c, st + j, t0 + ip, g.perm);
         if (DIGITS)

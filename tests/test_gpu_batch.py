@@ -55,6 +55,8 @@ def _mixed():
         Ins("lmm", I.lmm_curve80(80, 3), 130, 2, 3, m_offset=7),
         Ins("lmm", I.lmm_curve80(33, 1), 64, 1, 9, flags=rq.START_ZERO),
         Ins("mbs", I.mbs_paper(1), 1, 1, 2),
+        Ins("lmm", I.lmm_curve80(24, 2), 200, 2, 12, flags=rq.MC_PHILOX),
+        Ins("mbs", I.mbs_paper(120), 150, 2, 13, flags=rq.MC_PHILOX),
     ]
 
 

@@ -59,26 +59,28 @@ SMOOTH = [
     ("nf6d2", lambda: I.small_lmm(6, 2), 512, 2, 7),
     ("nf20d3", lambda: I.lmm_curve80(20, 3), 300, 2, 9),
     ("nf33d1", lambda: I.lmm_curve80(33, 1), 256, 1, 4),
+    ("nf12d2-mc", lambda: I.lmm_curve80(12, 2), 300, 2, 6, rq.MC_PHILOX),
 ]
 
 
-@pytest.mark.parametrize("name,mk,N,M,seed", SMOOTH, ids=[c[0] for c in SMOOTH])
-def test_caplet_adjoint_smooth_payoff_matches_fd(name, mk, N, M, seed):
+@pytest.mark.parametrize("name,mk,N,M,seed,flags", [c if len(c) == 6 else c + (0,) for c in SMOOTH],
+                         ids=[c[0] for c in SMOOTH])
+def test_caplet_adjoint_smooth_payoff_matches_fd(name, mk, N, M, seed, flags):
     model = mk()
     model.strike = np.zeros(model.n_fwd)          # no kink: delta*L_n(T_n)/numeraire
-    _say("adjoint smooth", name, N, M, seed)
-    r64 = rq.price_caplets(model, N, M, seed, precision="fp64", greeks=True, per_path=True)
-    th_o, pp_o = O.price_caplets(model, N, M, seed, per_path=True)
+    _say("adjoint smooth", name, N, M, seed, flags)
+    r64 = rq.price_caplets(model, N, M, seed, flags=flags, precision="fp64", greeks=True, per_path=True)
+    th_o, pp_o = O.price_caplets(model, N, M, seed, flags=flags, per_path=True)
     sc = model.delta * 0.06
     # prices from the adjoint kernel's forward pass: same per-path bar
     assert (np.abs(_np(r64.per_path) - pp_o) <= 1e-12 * (np.abs(pp_o) + sc * (model.n_fwd + 1))).all()
-    fd = fd_caplet_greeks(model, N, M, seed, h_rel=1e-5)
+    fd = fd_caplet_greeks(model, N, M, seed, h_rel=1e-5, flags=flags)
     g64 = _np(r64.greeks.theta)
     scale = np.abs(fd).max(axis=1, keepdims=True)
     err64 = np.abs(g64 - fd) / scale
     _say("fp64 adjoint vs FD max rel", float(err64.max()))
     assert err64.max() < 1e-7
-    r32 = rq.price_caplets(model, N, M, seed, precision="fp32", greeks=True)
+    r32 = rq.price_caplets(model, N, M, seed, flags=flags, precision="fp32", greeks=True)
     err32 = np.abs(_np(r32.greeks.theta) - fd) / scale
     _say("fp32 adjoint vs FD max rel", float(err32.max()))
     assert err32.max() < 1e-4
