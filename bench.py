@@ -253,7 +253,7 @@ def main(argv=None):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": _traffic_bytes("lmm80_3f_fp32_greeks_traffic.txt", ADJ_SOURCES),
-                     "kernel": "lmm_adjoint_kernel<80,3,float>", "kernel_ms": kms_g},
+                     "kernel": "lmm_adjoint_kernel<80,3,float,false>", "kernel_ms": kms_g},
     }
     line.update(out_extra)
     if args.batch != "off":
