@@ -28,6 +28,7 @@ START_RANDOM = 0
 START_ZERO = 1
 PERM_RANDOM = 2
 MC_PHILOX = 8
+LMM_EULER = 16
 
 _dp = C.POINTER(C.c_double)
 _u64p = C.POINTER(C.c_uint64)

@@ -44,6 +44,7 @@
 #define ORC_START_ZERO 1
 #define ORC_PERM_RANDOM 2
 #define ORC_MC_PHILOX 8
+#define ORC_LMM_EULER 16
 
 /* ------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
@@ -559,12 +560,13 @@ typedef struct {
     int n_fwd, d;
     double delta;
     const double *L0, *sigma, *b, *strike;
+    int euler;
 } orc_lmm_ctx;
 
 static void orc_lmm_fn(const void *c, const double *z, double *f)
 {
     const orc_lmm_ctx *m = (const orc_lmm_ctx *)c;
-    orc_lmm_path(m->n_fwd, m->d, m->delta, m->L0, m->sigma, m->b, m->strike, 1, 0, z, f);
+    orc_lmm_path(m->n_fwd, m->d, m->delta, m->L0, m->sigma, m->b, m->strike, 1, m->euler, z, f);
 }
 
 int orc_price_caplets(int n_fwd, int d, double delta, const double *L0, const double *sigma,
@@ -572,8 +574,9 @@ int orc_price_caplets(int n_fwd, int d, double delta, const double *L0, const do
                       int64_t m_offset, int flags, double *theta, double *per_path)
 {
     if (n_fwd < 1 || n_fwd > 1000 || d < 1 || d > 16 || !(delta > 0)) return ORC_EINVAL;
-    orc_lmm_ctx c = {n_fwd, d, delta, L0, sigma, b, strike};
-    return orc_price(n_fwd * d, n_fwd + 1, orc_lmm_fn, &c, N, M, seed, m_offset, flags, theta, per_path);
+    orc_lmm_ctx c = {n_fwd, d, delta, L0, sigma, b, strike, (flags & ORC_LMM_EULER) ? 1 : 0};
+    return orc_price(n_fwd * d, n_fwd + 1, orc_lmm_fn, &c, N, M, seed, m_offset, flags & ~ORC_LMM_EULER, theta,
+                     per_path);
 }
 
 typedef struct {

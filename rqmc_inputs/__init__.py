@@ -13,6 +13,10 @@ Sources for the shapes:
     payoff).  The paper prices a 1-factor constant-vol caplet; the larger
     workloads below keep its structure with 80 quarterly forwards and a
     3-factor PCA-reduced correlation.
+  * The paper's own LIBOR test case: the daily Treasury yield curve of
+    02/24/2012 (Table 3), interpolated by a cubic spline to 6-month points,
+    turned into bond prices and into initial forwards by eq. (BL), with
+    (t, T, delta, K, sigma) = (0, 5, 0.5, 0.01, 0.04).
   * Mortgage-backed security: Section "Pricing Mortgage-Backed Securities"
     with the paper's constants (i0, K1, K2, K3, K4, sigma^2) =
     (0.007, 0.01, -0.005, 10, 0.5, 0.0004).
@@ -29,6 +33,8 @@ __all__ = [
     "LmmModel", "MbsParams", "Instrument",
     "lmm_flat", "lmm_curve80", "pca_loadings",
     "mbs_paper", "cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "small_lmm",
+    "TREASURY_2012_02_24", "natural_cubic_spline", "treasury_bond_prices", "lmm_treasury_caplet",
+    "cfg_paper_libor",
 ]
 
 
@@ -199,3 +205,77 @@ def cfg5(n_inst: int = 256, seed: int = 5) -> List[Instrument]:
             d = int(rng.integers(1, 4))
             out.append(Instrument("lmm", lmm_curve80(n_fwd=nf, n_factors=d), N, M, 1000 + k))
     return out
+
+
+# ---------------------------------------------------------------------------
+# The paper's LIBOR test case (section "Pricing caplets in the LIBOR model")
+# ---------------------------------------------------------------------------
+# Table 3: daily Treasury yield curve rates on 02/24/2012, percent, at
+# maturities (years) 1/12, 1/4, 1/2, 1, 2, 3, 5, 7, 10, 20, 30.
+TREASURY_2012_02_24 = (
+    (1.0 / 12.0, 0.25, 0.5, 1.0, 2.0, 3.0, 5.0, 7.0, 10.0, 20.0, 30.0),
+    (0.08, 0.10, 0.14, 0.18, 0.31, 0.43, 0.89, 1.41, 1.98, 2.75, 3.10),
+)
+
+
+def natural_cubic_spline(x, y):
+    """The natural cubic spline through (x_i, y_i) (second derivative 0 at
+    both ends), returned as a function of t (array-like, inside [x_0, x_n]).
+    The second derivatives m_i solve the tridiagonal system
+    h_{i-1} m_{i-1} + 2 (h_{i-1} + h_i) m_i + h_i m_{i+1}
+        = 6 ((y_{i+1} - y_i)/h_i - (y_i - y_{i-1})/h_{i-1}),  m_0 = m_n = 0."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = len(x) - 1
+    h = np.diff(x)
+    A = np.zeros((n + 1, n + 1))
+    r = np.zeros(n + 1)
+    A[0, 0] = A[n, n] = 1.0
+    for i in range(1, n):
+        A[i, i - 1] = h[i - 1]
+        A[i, i] = 2.0 * (h[i - 1] + h[i])
+        A[i, i + 1] = h[i]
+        r[i] = 6.0 * ((y[i + 1] - y[i]) / h[i] - (y[i] - y[i - 1]) / h[i - 1])
+    m = np.linalg.solve(A, r)
+
+    def f(t):
+        t = np.asarray(t, dtype=np.float64)
+        i = np.clip(np.searchsorted(x, t, side="right") - 1, 0, n - 1)
+        a, b = x[i + 1] - t, t - x[i]
+        hi = h[i]
+        return (m[i] * a ** 3 + m[i + 1] * b ** 3) / (6.0 * hi) \
+            + (y[i] / hi - m[i] * hi / 6.0) * a + (y[i + 1] / hi - m[i + 1] * hi / 6.0) * b
+
+    return f
+
+
+def treasury_bond_prices(T):
+    """Zero-coupon bond prices B(0, T) from the Table 3 curve: the spline's
+    yield y(T) (percent) read as a semi-annually compounded rate,
+    B = (1 + y/200)^(-2T); B(0, 0) = 1."""
+    T = np.asarray(T, dtype=np.float64)
+    xs, ys = TREASURY_2012_02_24
+    y = natural_cubic_spline(xs, ys)(np.maximum(T, xs[0])) / 100.0
+    return np.where(T > 0, (1.0 + y / 2.0) ** (-2.0 * T), 1.0)
+
+
+def lmm_treasury_caplet(T: float = 5.0, delta: float = 0.5, K: float = 0.01, vol: float = 0.04) -> LmmModel:
+    """The paper's caplet: one factor, constant vol, forwards on the 6-month
+    grid initialised from the Treasury bond prices by eq. (BL),
+    L_n(0) = (B_n - B_{n+1}) / (delta B_{n+1}), and one caplet on the period
+    [T, T + delta] (forward n = T/delta) struck at K."""
+    nf = int(round(T / delta))
+    grid = np.arange(nf + 2, dtype=np.float64) * delta
+    B = treasury_bond_prices(grid)
+    L0 = (B[:-1] - B[1:]) / (delta * B[1:])
+    strike = np.full(nf, np.nan)
+    strike[nf - 1] = K
+    return LmmModel(n_fwd=nf, n_factors=1, delta=delta, L0=L0,
+                    sigma=np.full(nf + 1, vol, dtype=np.float64),
+                    loadings=np.ones((nf, 1), dtype=np.float64), strike=strike)
+
+
+def cfg_paper_libor(N: int = 1 << 16, M: int = 100, seed: int = 6) -> Instrument:
+    """The paper's LIBOR case (Table 3 curve, caplet on [5, 5.5], K = 1%,
+    sigma = 4%) with M = 100 replications as in the paper; s = 10."""
+    return Instrument("lmm", lmm_treasury_caplet(), N, M, seed)
