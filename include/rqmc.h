@@ -39,6 +39,13 @@
  *                   (j/4, i, 0, 0) under key (seed, m_global), mapped to
  *                   ((x >> 11) + 1/2) 2^-53.  Excludes the three flags above;
  *                   N is not limited by P_j.
+ *   RQ_LMM_EULER    rq_price_caplets only: the plain Euler step of the
+ *                   paper's discretised LIBOR SDE, L_n <- L_n + mu_n L_n delta
+ *                   + L_n sqrt(delta) a_n . Z, instead of the log-Euler step.
+ *                   Not with Greeks or RQ_PERM_RANDOM (RQ_EUNSUPPORTED), not
+ *                   in batches.  The FP32 form steps log2 L by log2 of the
+ *                   Euler factor, kept >= 2^-100 (an Euler step that would
+ *                   make a rate negative is outside the FP32 form).
  * Normals.  Dimension j of a path maps to z = Phi^{-1}(x) (Wichura's
  *   AS241 in FP64; the FP32 form folds r = min(x, 1-x) in FP64 first).
  * Memory.  Every pointer named "device" is a device (HBM) address on the
@@ -84,7 +91,8 @@ enum {
     RQ_START_ZERO = 1,
     RQ_PERM_RANDOM = 2,
     RQ_OUT_DIGITS = 4,
-    RQ_MC_PHILOX = 8
+    RQ_MC_PHILOX = 8,
+    RQ_LMM_EULER = 16
 };
 
 /* Limits of this build. */

@@ -247,7 +247,7 @@ rq_status check_common(int s, int64_t N, int M, int flags, int64_t m_offset, Geo
     if (N < 1) return fail(RQ_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
     if (M < 1) return fail(RQ_EINVAL, "M must be >= 1 (got %d)", M);
     if (m_offset < 0) return fail(RQ_EINVAL, "m_offset must be >= 0");
-    if (flags & ~(RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS | RQ_MC_PHILOX))
+    if (flags & ~(RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS | RQ_MC_PHILOX | RQ_LMM_EULER))
         return fail(RQ_EINVAL, "unknown flag bits 0x%x", flags);
     const bool mc = (flags & RQ_MC_PHILOX) != 0;
     if (mc && (flags & (RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS)))
@@ -559,6 +559,8 @@ rq_status plan_batch(const rq_instrument *inst, int n_inst, rq_precision prec, b
         p.m_offset = I.m_offset;
         p.flags = I.flags;
         if (I.flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "instrument %d: RQ_OUT_DIGITS applies to rq_sequence only", k);
+        if (I.flags & RQ_LMM_EULER)
+            return fail(RQ_EUNSUPPORTED, "instrument %d: the batch runs the log-Euler scheme only", k);
         if (I.kind == RQ_INST_LMM) {
             if ((st = check_lmm(I.lmm))) return fail(st, "instrument %d: %s", k, g_err.c_str());
             p.nf = I.lmm->n_fwd;
@@ -923,6 +925,7 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
                       void *ws, size_t ws_bytes, void *stream)
 {
     Geometry g;
+    if (flags & RQ_LMM_EULER) return fail(RQ_EINVAL, "RQ_LMM_EULER applies to rq_price_caplets only");
     rq_status stt = check_common(s, N, M, flags, m_offset, g);
     if (stt) return stt;
     if (!out) return fail(RQ_EINVAL, "out is NULL");
@@ -987,6 +990,10 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     rq_status stt = check_lmm(model);
     if (stt) return stt;
     if (flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "RQ_OUT_DIGITS applies to rq_sequence only");
+    if ((flags & RQ_LMM_EULER) && grad)
+        return fail(RQ_EUNSUPPORTED, "Greeks are computed for the log-Euler scheme only (RQ_LMM_EULER set)");
+    if ((flags & RQ_LMM_EULER) && (flags & RQ_PERM_RANDOM))
+        return fail(RQ_EUNSUPPORTED, "RQ_LMM_EULER is built for unpermuted Halton and Philox points");
     if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
     if (!out || !out->theta) return fail(RQ_EINVAL, "out->theta is NULL");
     if (grad && !grad->theta) return fail(RQ_EINVAL, "grad->theta is NULL");
@@ -1031,6 +1038,7 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     a.delta = model->delta;
     a.sqrt_delta = std::sqrt(model->delta);
     a.num0 = 1.0 + model->delta * model->L0[0];
+    a.euler = (flags & RQ_LMM_EULER) ? 1 : 0;
     {
         TimedRegion tr(st);
         if (greeks) RQ_HIP(rq::launch_lmm_adjoint(a, model->n_factors, prec == RQ_FP32, st));
@@ -1060,6 +1068,7 @@ rq_status rq_price_mbs(const rq_mbs_params *params, int64_t N, int M, uint64_t s
     rq_status stt = check_mbs(params);
     if (stt) return stt;
     if (flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "RQ_OUT_DIGITS applies to rq_sequence only");
+    if (flags & RQ_LMM_EULER) return fail(RQ_EINVAL, "RQ_LMM_EULER applies to rq_price_caplets only");
     if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
     if (!out || !out->theta) return fail(RQ_EINVAL, "out->theta is NULL");
     if (grad && !grad->theta) return fail(RQ_EINVAL, "grad->theta is NULL");

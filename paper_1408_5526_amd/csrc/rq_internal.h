@@ -52,6 +52,7 @@ constexpr int kStartZero = 1;
 constexpr int kPermRandom = 2;
 constexpr int kOutDigits = 4;
 constexpr int kMcPhilox = 8;
+constexpr int kLmmEuler = 16;
 
 // Arguments common to every kernel that generates points.
 struct SeqGeom {
@@ -121,6 +122,7 @@ struct LmmArgs {
     int n_out;
     int n_blk;               // blocks per replication
     double delta, sqrt_delta, num0;   // num0 = 1 + delta L_0(0)
+    int euler;               // pricing kernel only: plain Euler step instead of log-Euler
 };
 
 struct MbsArgs {

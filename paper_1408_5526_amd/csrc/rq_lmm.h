@@ -42,8 +42,10 @@ namespace rq {
 
 
 // GEN: 0 random-start Halton, 1 the same with permuted digits, 2 Philox
-// pseudo-random points (the comparison baseline).
-template <int NFC, int D, typename T, int GEN>
+// pseudo-random points (the comparison baseline).  EULER: the plain Euler
+// step of the paper's discretised SDE instead of the log-Euler step,
+//   L_n <- L_n + mu_n L_n delta + L_n sqrt(delta) a_n . z_k = L_n (1 + a_n . w).
+template <int NFC, int D, typename T, int GEN, bool EULER = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && GEN != 2 ? 4 : 1)))
 void lmm_kernel(LmmArgs a)
 {
@@ -106,19 +108,37 @@ void lmm_kernel(LmmArgs a)
                 for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
                 // form the (small) step increment first, then add it to the
                 // O(1) state once: one rounding at the state's scale per step
-                float e = ffma(q[0], w[0], q[6]);
+                if constexpr (EULER) {
+                    // plain Euler: L <- L (1 + a_n . w), i.e. X += log2(1 + a_n . w);
+                    // the argument is kept positive (an Euler step that would
+                    // make L negative is outside what the log form holds)
+                    float e = q[0] * w[0];
 #pragma unroll
-                for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
-                X[n] = ffma(e, on, X[n]);
+                    for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
+                    const float r = fmaxf(ffma(e, 0.693147180559945309f, 1.0f), 0x1p-100f);
+                    X[n] = ffma(__builtin_amdgcn_logf(r), on, X[n]);
+                } else {
+                    float e = ffma(q[0], w[0], q[6]);
+#pragma unroll
+                    for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
+                    X[n] = ffma(e, on, X[n]);
+                }
             } else {
                 const double dl = delta * X[n];
                 const double g = dl / (1.0 + dl);
 #pragma unroll
                 for (int f = 0; f < D; ++f) w[f] = ffma(g, r64(n, 3 + f), w[f]);
-                double e = r64(n, 6);
+                if constexpr (EULER) {   // plain Euler: L <- L + L (a_n . w)
+                    double e = r64(n, 0) * w[0];
 #pragma unroll
-                for (int f = 0; f < D; ++f) e = ffma(r64(n, f), w[f], e);
-                X[n] = X[n] * exp(e);
+                    for (int f = 1; f < D; ++f) e = ffma(r64(n, f), w[f], e);
+                    X[n] = ffma(X[n], e, X[n]);
+                } else {
+                    double e = r64(n, 6);
+#pragma unroll
+                    for (int f = 0; f < D; ++f) e = ffma(r64(n, f), w[f], e);
+                    X[n] = X[n] * exp(e);
+                }
             }
         };
         const unsigned alive = (unsigned)(nf - k);
@@ -196,41 +216,42 @@ void lmm_kernel(LmmArgs a)
     }
 }
 
-template <int NFC, int D, typename T, int GEN>
+template <int NFC, int D, typename T, int GEN, bool EULER>
 static hipError_t launch_t(const LmmArgs &a, hipStream_t st)
 {
     const int64_t blocks = (int64_t)a.n_blk * a.g.M;
-    hipLaunchKernelGGL((lmm_kernel<NFC, D, T, GEN>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((lmm_kernel<NFC, D, T, GEN, EULER>), dim3((unsigned)blocks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
-template <int D, typename T, int GEN>
+template <int D, typename T, int GEN, bool EULER>
 static hipError_t launch_d(const LmmArgs &a, hipStream_t st)
 {
-    if (a.n_fwd <= 16) return launch_t<16, D, T, GEN>(a, st);
-    if (a.n_fwd <= 32) return launch_t<32, D, T, GEN>(a, st);
-    if (a.n_fwd <= 48) return launch_t<48, D, T, GEN>(a, st);
-    if (a.n_fwd <= 64) return launch_t<64, D, T, GEN>(a, st);
-    return launch_t<80, D, T, GEN>(a, st);
+    if (a.n_fwd <= 16) return launch_t<16, D, T, GEN, EULER>(a, st);
+    if (a.n_fwd <= 32) return launch_t<32, D, T, GEN, EULER>(a, st);
+    if (a.n_fwd <= 48) return launch_t<48, D, T, GEN, EULER>(a, st);
+    if (a.n_fwd <= 64) return launch_t<64, D, T, GEN, EULER>(a, st);
+    return launch_t<80, D, T, GEN, EULER>(a, st);
 }
 
 // Pricing launch for one point generator (instantiated in rq_lmm.hip for
 // the Halton forms and in rq_lmm_mc.hip for the pseudo-random one, so that
 // they compile in parallel).
-template <int GEN>
+template <int GEN, bool EULER = false>
 static hipError_t launch_lmm_gen_t(const LmmArgs &a, int n_factors, int fp32, hipStream_t st)
 {
     switch (n_factors * 2 + (fp32 ? 1 : 0)) {
-    case 2: return launch_d<1, double, GEN>(a, st);
-    case 3: return launch_d<1, float, GEN>(a, st);
-    case 4: return launch_d<2, double, GEN>(a, st);
-    case 5: return launch_d<2, float, GEN>(a, st);
-    case 6: return launch_d<3, double, GEN>(a, st);
-    case 7: return launch_d<3, float, GEN>(a, st);
+    case 2: return launch_d<1, double, GEN, EULER>(a, st);
+    case 3: return launch_d<1, float, GEN, EULER>(a, st);
+    case 4: return launch_d<2, double, GEN, EULER>(a, st);
+    case 5: return launch_d<2, float, GEN, EULER>(a, st);
+    case 6: return launch_d<3, double, GEN, EULER>(a, st);
+    case 7: return launch_d<3, float, GEN, EULER>(a, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_lmm_mc(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
+hipError_t launch_lmm_euler(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
 
 }  // namespace rq

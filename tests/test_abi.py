@@ -122,3 +122,31 @@ def test_pca_loadings_validation():
     assert lib.rq_lmm_pca_loadings(4, 2, 0.25, 0.0, out) == rq.RQ_EINVAL
     assert lib.rq_lmm_pca_loadings(4, 2, 0.25, 0.1, None) == rq.RQ_EINVAL
     assert "NULL" in rq.last_error()
+
+
+def test_scheme_and_generator_flag_combinations():
+    m = I.lmm_treasury_caplet()
+    h = rq._LmmHost(m)
+    res = rq.rq_result(1, 0, 0, 0)
+    g = rq.rq_result(1, 0, 0, 0)
+
+    def call(flags, grad=None):
+        return rq.lib().rq_price_caplets(C.byref(h.c), 64, 1, 1, 0, flags, 0, C.byref(res),
+                                         C.byref(grad) if grad is not None else None, None,
+                                         C.c_void_p(256), 16, None)
+    # Euler with Greeks or permutations is refused; Philox excludes the Halton options
+    assert call(rq.LMM_EULER, g) == rq.RQ_EUNSUPPORTED and "log-Euler" in rq.last_error()
+    assert call(rq.LMM_EULER | rq.PERM_RANDOM) == rq.RQ_EUNSUPPORTED
+    assert call(rq.MC_PHILOX | rq.PERM_RANDOM) == rq.RQ_EINVAL and "RQ_MC_PHILOX" in rq.last_error()
+    assert call(rq.MC_PHILOX | rq.START_ZERO) == rq.RQ_EINVAL
+    # valid combinations get as far as the (too small) workspace
+    assert call(rq.LMM_EULER) == rq.RQ_EWORKSPACE
+    assert call(rq.LMM_EULER | rq.MC_PHILOX) == rq.RQ_EWORKSPACE
+    assert call(rq.MC_PHILOX) == rq.RQ_EWORKSPACE
+    # Euler is a LIBOR option only
+    p = rq._mbs_c(I.mbs_paper(12))
+    st = rq.lib().rq_price_mbs(C.byref(p), 64, 1, 1, 0, rq.LMM_EULER, 0, C.byref(res), None, None,
+                               C.c_void_p(256), 1 << 20, None)
+    assert st == rq.RQ_EINVAL and "caplets" in rq.last_error()
+    st = rq.lib().rq_sequence(4, 64, 1, 1, rq.LMM_EULER, 0, C.c_void_p(256), C.c_void_p(256), 1 << 20, None)
+    assert st == rq.RQ_EINVAL

@@ -40,3 +40,20 @@ def test_sd_slopes_rqmc_vs_mc(kind):
     assert -0.62 < out["mc"][0] < -0.38
     assert out["rqmc"][0] < out["mc"][0] - 0.08
     assert out["rqmc"][1][-1] < 0.6 * out["mc"][1][-1]
+
+
+def test_paper_caplet_convergence_rqmc_vs_mc():
+    # the paper's own case: Table 3 curve, plain Euler, caplet on [5, 5.5],
+    # K = 1%, sigma = 4%, M = 100 replications as in the paper
+    m = I.lmm_treasury_caplet()
+    Ns = [1 << 10, 1 << 12, 1 << 14, 1 << 16]
+    out = {}
+    for name, flags in (("rqmc", rq.LMM_EULER), ("mc", rq.LMM_EULER | rq.MC_PHILOX)):
+        sds = [float(rq.price_caplets(m, N, 100, 6, flags=flags, precision="fp64").sd[-1]) for N in Ns]
+        out[name] = (_slope(Ns, sds), sds)
+    print("[case] paper caplet", {k: (round(v[0], 3), [f"{x:.3g}" for x in v[1]]) for k, v in out.items()},
+          flush=True)
+    sys.stdout.flush()
+    assert -0.62 < out["mc"][0] < -0.38
+    assert out["rqmc"][0] < -0.75
+    assert out["rqmc"][1][-1] < out["mc"][1][-1] / 10

@@ -275,3 +275,37 @@ def test_mbs_full_size():
     assert (np.abs(_np(r.theta) - th_o) <= 1e-12 * (np.abs(th_o) + 1)).all()
     r32 = rq.price_mbs(c.model, c.N, c.M, c.seed, precision="fp32")
     assert (np.abs(_np(r32.theta) - th_o) <= 1e-6 * np.abs(th_o)).all()
+
+
+# ---------------------------------------------------------------------------
+# plain Euler scheme (the paper's discretisation) on the paper's own caplet
+# ---------------------------------------------------------------------------
+EULER = [
+    ("paper-caplet", lambda: I.lmm_treasury_caplet(), 1000, 3, 6, rq.LMM_EULER),
+    ("paper-caplet-mc", lambda: I.lmm_treasury_caplet(), 777, 2, 6, rq.LMM_EULER | rq.MC_PHILOX),
+    ("nf80d3", lambda: I.lmm_curve80(), 300, 2, 3, rq.LMM_EULER),
+    ("nf33d2", lambda: I.lmm_curve80(33, 2), 513, 2, 4, rq.LMM_EULER),
+]
+
+
+@pytest.mark.parametrize("name,mk,N,M,seed,flags", EULER, ids=[c[0] for c in EULER])
+def test_caplets_euler_fp64_per_path_and_fp32(name, mk, N, M, seed, flags):
+    model = mk()
+    _say("caplets euler", name, N, M, seed, flags)
+    r = rq.price_caplets(model, N, M, seed, flags=flags, precision="fp64", per_path=True)
+    th_o, pp_o = O.price_caplets(model, N, M, seed, flags=flags, per_path=True)
+    sc = _scales_lmm(model)
+    err = np.abs(_np(r.per_path) - pp_o) - 1e-12 * (np.abs(pp_o) + sc)
+    assert (err <= 0).all(), float(err.max())
+    assert (np.abs(_np(r.theta) - th_o) <= 1e-12 * (np.abs(th_o) + sc)).all()
+
+
+def test_caplets_euler_fp32_estimates():
+    model = I.lmm_treasury_caplet()
+    for flags in (rq.LMM_EULER, rq.LMM_EULER | rq.MC_PHILOX):
+        r = rq.price_caplets(model, 4133, 3, 6, flags=flags, precision="fp32")
+        th_o = O.price_caplets(model, 4133, 3, 6, flags=flags)
+        live = np.abs(th_o) > 0
+        rel = np.abs(_np(r.theta) - th_o)[live] / np.abs(th_o)[live]
+        _say("euler fp32 max rel", flags, float(rel.max()))
+        assert rel.max() <= 1e-6
