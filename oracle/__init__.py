@@ -29,6 +29,7 @@ START_ZERO = 1
 PERM_RANDOM = 2
 MC_PHILOX = 8
 LMM_EULER = 16
+PERM_PER_REP = 32
 
 _dp = C.POINTER(C.c_double)
 _u64p = C.POINTER(C.c_uint64)
@@ -58,6 +59,10 @@ def _load():
     lib.orc_radinv_R.argtypes = [C.c_uint64, C.c_int, _ip, C.c_uint64]
     lib.orc_point_from_R.restype = C.c_double
     lib.orc_point_from_R.argtypes = [C.c_uint64, C.c_uint64]
+    lib.orc_perm_rep.restype = C.c_int
+    lib.orc_perm_rep.argtypes = [C.c_uint64, C.c_uint64, C.c_int, C.c_int, _ip]
+    lib.orc_perm_rep_seed.restype = C.c_uint64
+    lib.orc_perm_rep_seed.argtypes = [C.c_uint64, C.c_uint64]
     lib.orc_philox4x64.restype = None
     lib.orc_philox4x64.argtypes = [_u64p, _u64p, _u64p]
     lib.orc_mc_point.restype = C.c_double
@@ -143,6 +148,19 @@ def perm(seed: int, j: int) -> np.ndarray:
     if st:
         raise RuntimeError(f"orc_perm status {st}")
     return out
+
+
+def perm_rep(seed: int, m_global: int, j: int) -> np.ndarray:
+    """The digit permutation of base j drawn by replication m_global."""
+    p = nth_prime(j)
+    out = np.empty(p, dtype=np.int32)
+    if _load().orc_perm_rep(seed, m_global, j, p, out.ctypes.data_as(_ip)):
+        raise RuntimeError("orc_perm_rep failed")
+    return out
+
+
+def perm_rep_seed(seed: int, m_global: int) -> int:
+    return int(_load().orc_perm_rep_seed(seed, m_global))
 
 
 def radinv_R(p: int, idx: int, sigma: Optional[np.ndarray] = None) -> int:

@@ -45,6 +45,7 @@
 #define ORC_PERM_RANDOM 2
 #define ORC_MC_PHILOX 8
 #define ORC_LMM_EULER 16
+#define ORC_PERM_PER_REP 32
 
 /* ------------------------------------------------------------------ */
 /* SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number
@@ -113,18 +114,32 @@ int orc_start(uint64_t seed, uint64_t m_global, int j, uint64_t P, int flags, ui
 
 /* Random digit permutation of base j (eq. (3), "picked at random"):
  * Fisher-Yates from the identity, step t = p-1 .. 1 swaps sigma[t] with
- * sigma[r], r uniform on [0, t], counter 2^60 + (j*4096 + t)*64 + attempt.
- * One permutation per (seed, base), shared by all replications. */
+ * sigma[r], r uniform on [0, t], counter 2^60 + (j*65536 + t)*64 + attempt
+ * (t < p <= 38873 < 65536).  One permutation per (seed, base), shared by all
+ * replications. */
 int orc_perm(uint64_t seed, int j, int p, int *sigma)
 {
     for (int t = 0; t < p; ++t) sigma[t] = t;
     for (int t = p - 1; t >= 1; --t) {
         uint64_t r;
-        uint64_t ctr = (1ULL << 60) + ((uint64_t)j * 4096ULL + (uint64_t)t) * 64ULL;
+        uint64_t ctr = (1ULL << 60) + ((uint64_t)j * 65536ULL + (uint64_t)t) * 64ULL;
         if (orc_uniform_below(seed, ctr, (uint64_t)(t + 1), &r)) return ORC_ERANGE;
         int tmp = sigma[t]; sigma[t] = sigma[(int)r]; sigma[(int)r] = tmp;
     }
     return ORC_OK;
+}
+
+/* The other reading of "random permutations": replication m_global draws
+ * its own permutation of every base -- the same Fisher-Yates, on the stream
+ * whose seed is output 2^62 + m_global of the seed's stream. */
+uint64_t orc_perm_rep_seed(uint64_t seed, uint64_t m_global)
+{
+    return orc_splitmix64(seed, (1ULL << 62) + m_global);
+}
+
+int orc_perm_rep(uint64_t seed, uint64_t m_global, int j, int p, int *sigma)
+{
+    return orc_perm(orc_perm_rep_seed(seed, m_global), j, p, sigma);
 }
 
 /* ------------------------------------------------------------------ */
@@ -436,10 +451,22 @@ static int orc_bases(int s, uint64_t seed, int flags, orc_base *bs)
         bs[j].p = (uint64_t)orc_nth_prime(j);
         bs[j].D = orc_digits(bs[j].p, &bs[j].P);
         bs[j].sigma = NULL;
-        if (flags & ORC_PERM_RANDOM) {
+        if (flags & (ORC_PERM_RANDOM | ORC_PERM_PER_REP)) {
             bs[j].sigma = (int *)malloc(sizeof(int) * bs[j].p);
-            if (orc_perm(seed, j, (int)bs[j].p, bs[j].sigma)) return ORC_ERANGE;
+            if (!(flags & ORC_PERM_PER_REP) && orc_perm(seed, j, (int)bs[j].p, bs[j].sigma)) return ORC_ERANGE;
         }
+    }
+    return ORC_OK;
+}
+
+/* Per-replication permutations: a private copy of the bases for
+ * replication m_global (freed by orc_bases_free). */
+static int orc_bases_rep(int s, uint64_t seed, uint64_t m_global, const orc_base *shared, orc_base *bs)
+{
+    for (int j = 0; j < s; ++j) {
+        bs[j] = shared[j];
+        bs[j].sigma = (int *)malloc(sizeof(int) * bs[j].p);
+        if (orc_perm_rep(seed, m_global, j, (int)bs[j].p, bs[j].sigma)) return ORC_ERANGE;
     }
     return ORC_OK;
 }
@@ -465,7 +492,7 @@ int orc_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t m_of
 {
     if (s < 1 || N < 1 || M < 1 || s > 4096) return ORC_EINVAL;
     if (flags & ORC_MC_PHILOX) {
-        if ((flags & (ORC_START_ZERO | ORC_PERM_RANDOM)) || out_R) return ORC_EINVAL;
+        if ((flags & (ORC_START_ZERO | ORC_PERM_RANDOM | ORC_PERM_PER_REP)) || out_R) return ORC_EINVAL;
 #pragma omp parallel for schedule(dynamic, 1)
         for (int m = 0; m < M; ++m)
             for (int64_t i = 0; i < N; ++i)
@@ -479,22 +506,29 @@ int orc_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t m_of
     if (!st) st = orc_check_N(s, N, bs);
     if (st) { orc_bases_free(s, bs); free(bs); return st; }
     int err = 0;
+    const int rep = (flags & ORC_PERM_PER_REP) != 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
     for (int m = 0; m < M; ++m) {
         orc_alg2 g;
+        orc_base *bm = bs;
+        if (rep) {
+            bm = (orc_base *)calloc((size_t)s, sizeof(orc_base));
+            if (orc_bases_rep(s, seed, (uint64_t)(m_offset + m), bs, bm)) err |= 1;
+        }
         for (int j = 0; j < s; ++j) {
             uint64_t n;
-            if (orc_start(seed, (uint64_t)(m_offset + m), j, bs[j].P, flags, &n)) { err |= 1; continue; }
-            if (gen) orc_alg2_init(&g, bs[j].p, bs[j].D, bs[j].sigma, n);
+            if (orc_start(seed, (uint64_t)(m_offset + m), j, bm[j].P, flags, &n)) { err |= 1; continue; }
+            if (gen) orc_alg2_init(&g, bm[j].p, bm[j].D, bm[j].sigma, n);
             for (int64_t i = 0; i < N; ++i) {
                 uint64_t R;
                 if (gen) { R = orc_alg2_R(&g); orc_alg2_next(&g); }
-                else R = orc_radinv_R(bs[j].p, bs[j].D, bs[j].sigma, (n + (uint64_t)i) % bs[j].P);
+                else R = orc_radinv_R(bm[j].p, bm[j].D, bm[j].sigma, (n + (uint64_t)i) % bm[j].P);
                 size_t o = ((size_t)m * (size_t)N + (size_t)i) * (size_t)s + (size_t)j;
                 if (out_R) out_R[o] = R;
-                if (out_x) out_x[o] = orc_point_from_R(R, bs[j].P);
+                if (out_x) out_x[o] = orc_point_from_R(R, bm[j].P);
             }
         }
+        if (rep) { orc_bases_free(s, bm); free(bm); }
     }
     orc_bases_free(s, bs);
     free(bs);
@@ -514,7 +548,7 @@ static int orc_price(int s, int n_out, orc_path_fn path, const void *ctx, int64_
 {
     if (s < 1 || N < 1 || M < 1 || s > 4096 || n_out < 1) return ORC_EINVAL;
     const int mc = (flags & ORC_MC_PHILOX) != 0;
-    if (mc && (flags & (ORC_START_ZERO | ORC_PERM_RANDOM))) return ORC_EINVAL;
+    if (mc && (flags & (ORC_START_ZERO | ORC_PERM_RANDOM | ORC_PERM_PER_REP))) return ORC_EINVAL;
     orc_base *bs = (orc_base *)calloc((size_t)s, sizeof(orc_base));
     int st = mc ? ORC_OK : orc_bases(s, seed, flags, bs);
     if (!st && !mc) st = orc_check_N(s, N, bs);
@@ -526,10 +560,15 @@ static int orc_price(int s, int n_out, orc_path_fn path, const void *ctx, int64_
         double *z = (double *)malloc(sizeof(double) * (size_t)s);
         double *f = (double *)malloc(sizeof(double) * (size_t)n_out);
         orc_acc *acc = (orc_acc *)calloc((size_t)n_out, sizeof(orc_acc));
+        orc_base *bm = bs;
+        if (!mc && (flags & ORC_PERM_PER_REP)) {
+            bm = (orc_base *)calloc((size_t)s, sizeof(orc_base));
+            if (orc_bases_rep(s, seed, (uint64_t)(m_offset + m), bs, bm)) err |= 1;
+        }
         for (int j = 0; j < s && !mc; ++j) {
             uint64_t n;
-            if (orc_start(seed, (uint64_t)(m_offset + m), j, bs[j].P, flags, &n)) err |= 1;
-            orc_alg2_init(&g[j], bs[j].p, bs[j].D, bs[j].sigma, n);
+            if (orc_start(seed, (uint64_t)(m_offset + m), j, bm[j].P, flags, &n)) err |= 1;
+            orc_alg2_init(&g[j], bm[j].p, bm[j].D, bm[j].sigma, n);
         }
         for (int64_t i = 0; i < N; ++i) {
             for (int j = 0; j < s; ++j) {
@@ -537,7 +576,7 @@ static int orc_price(int s, int n_out, orc_path_fn path, const void *ctx, int64_
                 if (mc) {
                     x = orc_mc_point(seed, (uint64_t)(m_offset + m), (uint64_t)i, j);
                 } else {
-                    x = orc_point_from_R(orc_alg2_R(&g[j]), bs[j].P);
+                    x = orc_point_from_R(orc_alg2_R(&g[j]), bm[j].P);
                     orc_alg2_next(&g[j]);
                 }
                 z[j] = orc_ppnd16(x);
@@ -550,6 +589,7 @@ static int orc_price(int s, int n_out, orc_path_fn path, const void *ctx, int64_
         }
         for (int o = 0; o < n_out; ++o) theta[(size_t)m * n_out + o] = orc_acc_val(&acc[o]) / (double)N;
         free(g); free(z); free(f); free(acc);
+        if (bm != bs) { orc_bases_free(s, bm); free(bm); }
     }
     orc_bases_free(s, bs);
     free(bs);

@@ -169,7 +169,7 @@ bool uniform_below(uint64_t seed, uint64_t ctr0, uint64_t range, uint64_t &out)
 // Host tables of the point geometry: BaseEnt[s] followed (when permuted)
 // by the packed u16 permutations.  Fisher-Yates per base from the
 // identity: step t = p-1..1 swaps sigma[t] and sigma[r], r uniform on
-// [0, t] with counters 2^60 + (j*4096 + t)*64 + attempt.
+// [0, t] with counters 2^60 + (j*65536 + t)*64 + attempt (t < p < 65536).
 struct PointTables {
     std::vector<BaseEnt> base;
     std::vector<uint16_t> perm;
@@ -206,7 +206,7 @@ rq_status build_point_tables(int s, const Geometry &g, uint64_t seed, int flags,
             for (uint32_t a = 0; a < p; ++a) sg[a] = (uint16_t)a;
             for (uint32_t st = p - 1; st >= 1; --st) {
                 uint64_t r;
-                const uint64_t ctr = (1ull << 60) + ((uint64_t)j * 4096ull + st) * 64ull;
+                const uint64_t ctr = (1ull << 60) + ((uint64_t)j * 65536ull + st) * 64ull;
                 if (!uniform_below(seed, ctr, (uint64_t)st + 1, r))
                     return fail(RQ_ERANGE, "permutation draw exhausted its attempts");
                 std::swap(sg[st], sg[r]);
