@@ -29,9 +29,18 @@
  *                   suffices; the others repeat it).
  *   RQ_PERM_RANDOM  one random digit permutation per base (eq. (3)),
  *                   shared by all replications; digits above the top
- *                   nonzero digit stay unpermuted.
+ *                   nonzero digit stay unpermuted.  Fisher-Yates from the
+ *                   identity with SplitMix64 draws at counters
+ *                   2^60 + (j 65536 + t) 64 + attempt.
  *   RQ_OUT_DIGITS   rq_sequence only: emit the exact integers R (uint64)
  *                   instead of the FP64 points.
+ *   RQ_PERM_PER_REP the other reading of the random permutations: every
+ *                   replication draws its own permutation of every base
+ *                   (same Fisher-Yates, on the SplitMix64 stream seeded with
+ *                   output 2^62 + m_global of the seed's stream); generated
+ *                   on the device, M * (sum of the s primes) uint16 of
+ *                   workspace.  Alternative to RQ_PERM_RANDOM; not in
+ *                   batches.
  *   RQ_MC_PHILOX    pseudo-random points instead of Halton (the paper's
  *                   Philox comparison): coordinate j of point i of
  *                   replication m_global is word (j mod 4) of Philox4x64-10
@@ -92,7 +101,8 @@ enum {
     RQ_PERM_RANDOM = 2,
     RQ_OUT_DIGITS = 4,
     RQ_MC_PHILOX = 8,
-    RQ_LMM_EULER = 16
+    RQ_LMM_EULER = 16,
+    RQ_PERM_PER_REP = 32
 };
 
 /* Limits of this build. */

@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(HERE, "librqmc.so")
 
 RQ_OK, RQ_EINVAL, RQ_ERANGE, RQ_ENOMEM, RQ_EHIP, RQ_EWORKSPACE, RQ_EUNSUPPORTED = range(7)
 FP64, FP32 = 0, 1
-START_RANDOM, START_ZERO, PERM_RANDOM, OUT_DIGITS, MC_PHILOX, LMM_EULER = 0, 1, 2, 4, 8, 16
+START_RANDOM, START_ZERO, PERM_RANDOM, OUT_DIGITS, MC_PHILOX, LMM_EULER, PERM_PER_REP = 0, 1, 2, 4, 8, 16, 32
 
 _dp = C.POINTER(C.c_double)
 

@@ -196,7 +196,7 @@ rq_status build_point_tables(int s, const Geometry &g, uint64_t seed, int flags,
         b.Pd = (double)b.P;
         b.invP = 1.0 / b.Pd;
         b.perm_off = off;
-        if (flags & RQ_PERM_RANDOM) off += (uint32_t)p;
+        if (flags & (RQ_PERM_RANDOM | RQ_PERM_PER_REP)) off += (uint32_t)p;
     }
     if (flags & RQ_PERM_RANDOM) {
         t.perm.resize(off);
@@ -216,10 +216,12 @@ rq_status build_point_tables(int s, const Geometry &g, uint64_t seed, int flags,
     return RQ_OK;
 }
 
-// Workspace layout.  Region offsets are 256-byte aligned.
+// Workspace layout.  Region offsets are 256-byte aligned.  Per-replication
+// permutations (rperm, [M][sum of the primes]) are generated on the device.
 struct Layout {
-    size_t base = 0, perm = 0, model = 0, starts = 0, partial = 0, total = 0;
+    size_t base = 0, perm = 0, model = 0, starts = 0, rperm = 0, partial = 0, total = 0;
     size_t host_bytes = 0;   // bytes staged from the host (base | perm | model)
+    int64_t perm_stride = 0; // per-replication table length (elements)
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -236,7 +238,13 @@ Layout layout(int s, const Geometry &g, int M, int flags, size_t model_bytes, si
     L.model = L.perm + al(perm_elems * sizeof(uint16_t));
     L.host_bytes = L.model + model_bytes;
     L.starts = al(L.host_bytes);
-    L.partial = L.starts + al(sizeof(StartEnt) * (size_t)M * (size_t)g.n_seg * (size_t)s);
+    L.rperm = L.starts + al(sizeof(StartEnt) * (size_t)M * (size_t)g.n_seg * (size_t)s);
+    size_t rperm_bytes = 0;
+    if (flags & RQ_PERM_PER_REP) {
+        for (int j = 0; j < s; ++j) L.perm_stride += pr[j];
+        rperm_bytes = (size_t)M * (size_t)L.perm_stride * sizeof(uint16_t);
+    }
+    L.partial = L.rperm + al(rperm_bytes);
     L.total = L.partial + al(partial_bytes);
     return L;
 }
@@ -247,11 +255,13 @@ rq_status check_common(int s, int64_t N, int M, int flags, int64_t m_offset, Geo
     if (N < 1) return fail(RQ_EINVAL, "N must be >= 1 (got %lld)", (long long)N);
     if (M < 1) return fail(RQ_EINVAL, "M must be >= 1 (got %d)", M);
     if (m_offset < 0) return fail(RQ_EINVAL, "m_offset must be >= 0");
-    if (flags & ~(RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS | RQ_MC_PHILOX | RQ_LMM_EULER))
+    if (flags & ~(RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS | RQ_MC_PHILOX | RQ_LMM_EULER | RQ_PERM_PER_REP))
         return fail(RQ_EINVAL, "unknown flag bits 0x%x", flags);
     const bool mc = (flags & RQ_MC_PHILOX) != 0;
-    if (mc && (flags & (RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS)))
-        return fail(RQ_EINVAL, "RQ_MC_PHILOX excludes RQ_START_ZERO, RQ_PERM_RANDOM and RQ_OUT_DIGITS");
+    if (mc && (flags & (RQ_START_ZERO | RQ_PERM_RANDOM | RQ_OUT_DIGITS | RQ_PERM_PER_REP)))
+        return fail(RQ_EINVAL, "RQ_MC_PHILOX excludes RQ_START_ZERO, RQ_PERM_RANDOM, RQ_PERM_PER_REP and RQ_OUT_DIGITS");
+    if ((flags & RQ_PERM_RANDOM) && (flags & RQ_PERM_PER_REP))
+        return fail(RQ_EINVAL, "RQ_PERM_RANDOM and RQ_PERM_PER_REP are alternatives");
     if (s > RQ_MAX_DIM) return fail(RQ_ERANGE, "s = %d beyond the %d supported bases", s, RQ_MAX_DIM);
     if (m_offset + (int64_t)M > RQ_MAX_REPLICATION)
         return fail(RQ_ERANGE, "m_offset + M beyond 2^40");
@@ -290,6 +300,20 @@ rq_status stage_and_setup(const PointTables &pt, const std::vector<uint8_t> &mod
     a.base_dev = reinterpret_cast<BaseEnt *>(ws + L.base);
     a.starts = reinterpret_cast<StartEnt *>(ws + L.starts);
     a.perm = (flags & RQ_PERM_RANDOM) ? reinterpret_cast<const uint16_t *>(ws + L.perm) : nullptr;
+    a.perm_stride = 0;
+    if (flags & RQ_PERM_PER_REP) {   // each replication's permutations, drawn on the device
+        rq::PermArgs pa;
+        pa.table = reinterpret_cast<uint16_t *>(ws + L.rperm);
+        pa.base = reinterpret_cast<const BaseEnt *>(ws + L.base);
+        pa.seed = seed;
+        pa.m_offset = m_offset;
+        pa.stride = L.perm_stride;
+        pa.s = s;
+        pa.M = M;
+        RQ_HIP(rq::launch_perm(pa, st));
+        a.perm = pa.table;
+        a.perm_stride = L.perm_stride;
+    }
     a.seed = seed;
     a.m_offset = m_offset;
     a.s = s;
@@ -308,10 +332,15 @@ rq::SeqGeom seq_geom(const Layout &L, const Geometry &g, uint8_t *ws, int s, int
     sg.base = reinterpret_cast<const BaseEnt *>(ws + L.base);
     sg.starts = reinterpret_cast<const StartEnt *>(ws + L.starts);
     sg.perm = (flags & RQ_PERM_RANDOM) ? reinterpret_cast<const uint16_t *>(ws + L.perm) : nullptr;
+    sg.perm_stride = 0;
+    if (flags & RQ_PERM_PER_REP) {
+        sg.perm = reinterpret_cast<const uint16_t *>(ws + L.rperm);
+        sg.perm_stride = L.perm_stride;
+    }
     sg.s = s;
     sg.M = M;
     sg.n_seg = g.n_seg;
-    sg.perm_on = (flags & RQ_PERM_RANDOM) ? 1 : 0;
+    sg.perm_on = (flags & (RQ_PERM_RANDOM | RQ_PERM_PER_REP)) ? 1 : 0;
     sg.mc = (flags & RQ_MC_PHILOX) ? 1 : 0;
     sg.seed = seed;
     sg.m_offset = m_offset;
@@ -561,6 +590,8 @@ rq_status plan_batch(const rq_instrument *inst, int n_inst, rq_precision prec, b
         if (I.flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "instrument %d: RQ_OUT_DIGITS applies to rq_sequence only", k);
         if (I.flags & RQ_LMM_EULER)
             return fail(RQ_EUNSUPPORTED, "instrument %d: the batch runs the log-Euler scheme only", k);
+        if (I.flags & RQ_PERM_PER_REP)
+            return fail(RQ_EUNSUPPORTED, "instrument %d: the batch uses shared permutations only", k);
         if (I.kind == RQ_INST_LMM) {
             if ((st = check_lmm(I.lmm))) return fail(st, "instrument %d: %s", k, g_err.c_str());
             p.nf = I.lmm->n_fwd;
@@ -992,7 +1023,7 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     if (flags & RQ_OUT_DIGITS) return fail(RQ_EINVAL, "RQ_OUT_DIGITS applies to rq_sequence only");
     if ((flags & RQ_LMM_EULER) && grad)
         return fail(RQ_EUNSUPPORTED, "Greeks are computed for the log-Euler scheme only (RQ_LMM_EULER set)");
-    if ((flags & RQ_LMM_EULER) && (flags & RQ_PERM_RANDOM))
+    if ((flags & RQ_LMM_EULER) && (flags & (RQ_PERM_RANDOM | RQ_PERM_PER_REP)))
         return fail(RQ_EUNSUPPORTED, "RQ_LMM_EULER is built for unpermuted Halton and Philox points");
     if (prec != RQ_FP64 && prec != RQ_FP32) return fail(RQ_EINVAL, "unknown precision %d", (int)prec);
     if (!out || !out->theta) return fail(RQ_EINVAL, "out->theta is NULL");

@@ -53,12 +53,14 @@ constexpr int kPermRandom = 2;
 constexpr int kOutDigits = 4;
 constexpr int kMcPhilox = 8;
 constexpr int kLmmEuler = 16;
+constexpr int kPermPerRep = 32;
 
 // Arguments common to every kernel that generates points.
 struct SeqGeom {
     const BaseEnt *base;     // [s]
     const StartEnt *starts;  // [M][n_seg][s]
     const uint16_t *perm;    // packed permutations or nullptr
+    int64_t perm_stride;     // elements between replications' tables (0: shared by all)
     int s;
     int M;
     int n_seg;
@@ -75,6 +77,7 @@ struct SetupArgs {
     BaseEnt *base_dev;       // read
     StartEnt *starts;        // written [M][n_seg][s]
     const uint16_t *perm;
+    int64_t perm_stride;     // as in SeqGeom
     uint64_t seed;
     int64_t m_offset;
     int s, M, n_seg;
@@ -150,8 +153,20 @@ struct FinalizeArgs {
     int M, n_out;
 };
 
+// Per-replication digit permutations: table[m][perm_off_j + a], one
+// Fisher-Yates per (replication, base).
+struct PermArgs {
+    uint16_t *table;
+    const BaseEnt *base;
+    uint64_t seed;
+    int64_t m_offset;
+    int64_t stride;          // sum of the s primes
+    int s, M;
+};
+
 // Launchers (each returns the hipError_t of its launch).
 hipError_t launch_setup(const SetupArgs &a, hipStream_t st);
+hipError_t launch_perm(const PermArgs &a, hipStream_t st);
 hipError_t launch_sequence(const SeqGeom &g, int flags, void *out, hipStream_t st);
 hipError_t launch_lmm(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
 hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);

@@ -95,7 +95,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                 x = mc.point(a.g.seed, (uint64_t)(a.g.m_offset + m), (uint64_t)i, j);
             } else {
                 const PointCtx c = load_base(a.g.base, j);
-                x = a.g.perm_on ? radinv_x<true, !kF32>(c, st + j, t, a.g.perm)
+                x = a.g.perm_on ? radinv_x<true, !kF32>(c, st + j, t, a.g.perm + (size_t)m * a.g.perm_stride)
                                 : radinv_x<false, !kF32>(c, st + j, t, a.g.perm);
             }
             w[f] = sqd * inv_normal(x, T(0));

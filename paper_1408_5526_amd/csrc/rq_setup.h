@@ -61,7 +61,7 @@ __device__ __forceinline__ void setup_one(const SetupArgs &a, int64_t idx)
     if (base >= b.P) base -= b.P;
     const uint64_t hi = base / b.pL;
     const uint32_t nlo = (uint32_t)(base - hi * b.pL);
-    const uint16_t *sg = (a.flags & kPermRandom) ? a.perm + b.perm_off : nullptr;
+    const uint16_t *sg = a.perm ? a.perm + (size_t)m * a.perm_stride + b.perm_off : nullptr;
     const uint32_t nd = b.D - b.L;
     uint64_t h0 = hi;
     uint64_t h1 = hi + 1;

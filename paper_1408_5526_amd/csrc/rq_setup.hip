@@ -12,6 +12,43 @@ __global__ __launch_bounds__(256) void setup_kernel(SetupArgs a)
     setup_one(a, idx);
 }
 
+// Replication m draws its own permutation of every base: Fisher-Yates from
+// the identity, step t = p-1..1 swapping sigma[t] and sigma[r], r uniform on
+// [0, t] by rejection from the SplitMix64 stream seeded with output
+// 2^62 + m_global of the seed's stream, counters 2^60 + (j 65536 + t) 64 + a.
+// One thread per (replication, base); its table slice is private.
+__global__ __launch_bounds__(256) void perm_kernel(PermArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)a.M * a.s) return;
+    const int j = (int)(idx % a.s);
+    const int64_t m = idx / a.s;
+    const uint32_t p = a.base[j].p;
+    uint16_t *sg = a.table + (size_t)m * a.stride + a.base[j].perm_off;
+    const uint64_t sm = sm64_at(a.seed, (1ull << 62) + (uint64_t)(a.m_offset + m));
+    for (uint32_t v = 0; v < p; ++v) sg[v] = (uint16_t)v;
+    for (uint32_t t = p - 1; t >= 1; --t) {
+        const uint64_t range = (uint64_t)t + 1;
+        const uint64_t rem = (0ull - range) % range;
+        const uint64_t ctr0 = (1ull << 60) + ((uint64_t)j * 65536ull + t) * 64ull;
+        uint64_t r = 0;
+        for (uint64_t at = 0; at < 64; ++at) {   // a draw is rejected with probability < 2^-48
+            const uint64_t u = sm64_at(sm, ctr0 + at);
+            if (rem == 0 || u < 0ull - rem) { r = u % range; break; }
+        }
+        const uint16_t tmp = sg[t];
+        sg[t] = sg[r];
+        sg[r] = tmp;
+    }
+}
+
+hipError_t launch_perm(const PermArgs &a, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.M * a.s;
+    hipLaunchKernelGGL(perm_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_setup(const SetupArgs &a, hipStream_t st)
 {
     const int64_t total = (int64_t)a.M * a.n_seg * a.s;
@@ -50,7 +87,7 @@ __global__ __launch_bounds__(256) void sequence_kernel(SeqGeom g, int64_t tiles_
             continue;
         }
         const PointCtx c = load_base(g.base, j);
-        const double R = radinv_R<PERM>(c, st + j, t0 + ip, g.perm);
+        const double R = radinv_R<PERM>(c, st + j, t0 + ip, g.perm + (size_t)m * g.perm_stride);
         if (DIGITS)
             ((uint64_t *)out)[obase + e] = (uint64_t)R;
         else
@@ -62,7 +99,7 @@ hipError_t launch_sequence(const SeqGeom &g, int flags, void *out, hipStream_t s
 {
     const int64_t tiles = (g.N + kTile - 1) / kTile;
     const int64_t blocks = tiles * g.M;
-    const bool perm = (flags & kPermRandom) != 0;
+    const bool perm = g.perm_on != 0;   // one shared table or one per replication
     const bool dig = (flags & kOutDigits) != 0;
     auto k = perm ? (dig ? sequence_kernel<true, true> : sequence_kernel<true, false>)
                   : (dig ? sequence_kernel<false, true> : sequence_kernel<false, false>);

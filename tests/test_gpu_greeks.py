@@ -60,6 +60,7 @@ SMOOTH = [
     ("nf20d3", lambda: I.lmm_curve80(20, 3), 300, 2, 9),
     ("nf33d1", lambda: I.lmm_curve80(33, 1), 256, 1, 4),
     ("nf12d2-mc", lambda: I.lmm_curve80(12, 2), 300, 2, 6, rq.MC_PHILOX),
+    ("nf12d2-permrep", lambda: I.lmm_curve80(12, 2), 300, 2, 6, rq.PERM_PER_REP),
 ]
 
 

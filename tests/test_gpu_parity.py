@@ -52,6 +52,8 @@ SEQ = [
     (360, 700, 2, 2, 0),
     (1, 1, 1, 3, 0),
     (37, 1000, 3, 7, rq.MC_PHILOX),
+    (37, 1000, 3, 7, rq.PERM_PER_REP),
+    (12, 300, 4, 5, rq.PERM_PER_REP | rq.START_ZERO),
 ]
 
 
@@ -150,6 +152,7 @@ LMM = [
     ("nf64d3-n1", lambda: I.lmm_curve80(64, 3), 1, 1, 8, 0),
     ("nf20d3-mc", lambda: I.lmm_curve80(20, 3), 513, 2, 5, rq.MC_PHILOX),
     ("nf80d3-mc", lambda: I.lmm_curve80(), 300, 2, 3, rq.MC_PHILOX),
+    ("nf20d3-permrep", lambda: I.lmm_curve80(20, 3), 513, 3, 5, rq.PERM_PER_REP),
 ]
 
 
@@ -184,6 +187,7 @@ LMM32 = [
     ("nf80d3", lambda: I.lmm_curve80(), 4133, 2, 3, 0),
     ("nf33d1-perm", lambda: I.lmm_curve80(33, 1), 4097, 2, 9, rq.PERM_RANDOM),
     ("nf20d3-mc", lambda: I.lmm_curve80(20, 3), 4200, 2, 5, rq.MC_PHILOX),
+    ("nf33d1-permrep", lambda: I.lmm_curve80(33, 1), 4097, 3, 9, rq.PERM_PER_REP),
 ]
 
 
@@ -244,6 +248,7 @@ MBS = [
     ("m1", lambda: I.mbs_paper(1), 64, 2, 5, 0),
     ("m240-zero", lambda: I.mbs_paper(240, 0.01), 300, 1, 6, rq.START_ZERO),
     ("m360-mc", lambda: I.mbs_paper(360), 700, 2, 8, rq.MC_PHILOX),
+    ("m120-permrep", lambda: I.mbs_paper(120), 600, 3, 8, rq.PERM_PER_REP),
 ]
 
 
@@ -309,3 +314,15 @@ def test_caplets_euler_fp32_estimates():
         rel = np.abs(_np(r.theta) - th_o)[live] / np.abs(th_o)[live]
         _say("euler fp32 max rel", flags, float(rel.max()))
         assert rel.max() <= 1e-6
+
+
+def test_per_replication_permutations_m_offset_and_large_bases():
+    # the replication key is m_global: an m_offset split reproduces the
+    # whole; s = 600 reaches bases above 4096 (the counter stride)
+    _say("perm per rep m_offset")
+    a = _np(rq.sequence(600, 300, 3, 17, rq.PERM_PER_REP | rq.OUT_DIGITS))
+    b = np.concatenate([_np(rq.sequence(600, 300, 1, 17, rq.PERM_PER_REP | rq.OUT_DIGITS, m_offset=0)),
+                        _np(rq.sequence(600, 300, 2, 17, rq.PERM_PER_REP | rq.OUT_DIGITS, m_offset=1))])
+    assert np.array_equal(a, b)
+    xo, Ro = O.sequence(600, 300, 3, 17, O.PERM_PER_REP)
+    assert np.array_equal(a.astype(np.uint64), Ro)
