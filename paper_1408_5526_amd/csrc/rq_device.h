@@ -10,6 +10,33 @@
 
 namespace rq {
 
+// Read-only parameter tables are read through the constant address space:
+// the kernel never writes them, so the compiler may use scalar loads even
+// after the kernel has stored to global memory.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const void *p)
+{
+    return (cptr<T>)p;
+}
+
+// A wave-uniform struct read through the constant address space (scalar
+// loads; the fields the caller never uses are not loaded).
+template <typename S>
+__device__ __forceinline__ S load_uniform(const void *p)
+{
+    static_assert(sizeof(S) % 4 == 0, "struct size must be a multiple of 4");
+    const cptr<uint32_t> q = as_const<uint32_t>(p);
+    uint32_t w[sizeof(S) / 4];
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(S) / 4; ++i) w[i] = q[i];
+    S out;
+    __builtin_memcpy(&out, w, sizeof(S));
+    return out;
+}
+
 // ---------------------------------------------------------------------------
 // Radical inverse (eqs. (1)-(3)) of the index (n + i) mod P for one lane.
 //
@@ -47,18 +74,37 @@ __device__ __forceinline__ PointCtx load_base(const BaseEnt *__restrict__ base, 
     return c;
 }
 
+// The same, for a dimension j shared by the whole wave (every pricing
+// kernel: j is the time step's dimension): scalar loads through the constant
+// address space, so the digit loop's trip count and constants arrive in
+// scalar registers after a short scalar-cache round trip.
+__device__ __forceinline__ PointCtx load_base_uniform(const BaseEnt *base, int j)
+{
+    const BaseEnt b = load_uniform<BaseEnt>(base + j);
+    PointCtx c;
+    c.pd = b.pd;
+    c.invp = b.invp_up;
+    c.pDLd = b.pDLd;
+    c.Pd = b.Pd;
+    c.invP = b.invP;
+    c.L = b.L;
+    c.pL = b.pL;
+    c.perm_off = b.perm_off;
+    return c;
+}
+
 // R of the lane's point as an exact FP64 integer.  The carry picks the high
 // part as Rhi[0] + c (Rhi[1] - Rhi[0]): arithmetic on two scalars instead of
 // a per-lane selected load.  Digits go two at a time to keep the loop free
 // of register shuffles.
 template <bool PERM>
-__device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt *__restrict__ e,
-                                           uint32_t t, const uint16_t *__restrict__ perm)
+__device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt &e, uint32_t t,
+                                           const uint16_t *__restrict__ perm)
 {
-    uint32_t vi = e->nlo + t;                 // < 2 p^L <= 2^31
+    uint32_t vi = e.nlo + t;                  // < 2 p^L <= 2^31
     const bool carry = vi >= c.pL;
     vi -= carry ? c.pL : 0u;
-    const double rhi = __builtin_fma(carry ? 1.0 : 0.0, e->drhi, e->rhi0);
+    const double rhi = __builtin_fma(carry ? 1.0 : 0.0, e.drhi, e.rhi0);
     double v = (double)vi;
     double R = 0.0;
     if (!PERM) {
@@ -76,7 +122,7 @@ __device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt *__
             R = __builtin_fma(R, c.pd, __builtin_fma(-q1, c.pd, v));
         }
     } else {
-        const bool hz = (e->hz >> (carry ? 1 : 0)) & 1u;
+        const bool hz = (e.hz >> (carry ? 1 : 0)) & 1u;
         const uint16_t *sg = perm + c.perm_off;
         for (uint32_t q = 0; q < c.L; ++q) {
             const double qt = __builtin_trunc(v * c.invp);
@@ -92,8 +138,8 @@ __device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt *__
 // The point RN(R / P).  EXACT = false forms R * RN(1/P) instead, within
 // two ulps of it (used where the point only feeds FP32 arithmetic).
 template <bool PERM, bool EXACT = true>
-__device__ __forceinline__ double radinv_x(const PointCtx &c, const StartEnt *__restrict__ e,
-                                           uint32_t t, const uint16_t *__restrict__ perm)
+__device__ __forceinline__ double radinv_x(const PointCtx &c, const StartEnt &e, uint32_t t,
+                                           const uint16_t *__restrict__ perm)
 {
     const double R = radinv_R<PERM>(c, e, t, perm);
     return EXACT ? R / c.Pd : R * c.invP;
@@ -292,18 +338,6 @@ struct Acc {
     double s, c;
 };
 
-// Read-only parameter tables are read through the constant address space:
-// the kernel never writes them, so the compiler may use scalar loads even
-// after the kernel has stored to global memory.
-template <typename T>
-using cptr = const __attribute__((address_space(4))) T *;
-
-template <typename T>
-__device__ __forceinline__ cptr<T> as_const(const void *p)
-{
-    return (cptr<T>)p;
-}
-
 // ---------------------------------------------------------------------------
 // Pseudo-random points (the comparison baseline): Philox4x64-10 (Salmon,
 // Moraes, Dror & Shaw, SC'11).  A round maps the counter (c0, c1, c2, c3)
@@ -368,21 +402,6 @@ __device__ __forceinline__ cptr<T> opaque_u(cptr<T> p)
     uint64_t u = (uint64_t)p;
     asm volatile("" : "+s"(u));
     return (cptr<T>)u;
-}
-
-// A wave-uniform struct read through the constant address space (scalar
-// loads; the fields the caller never uses are not loaded).
-template <typename S>
-__device__ __forceinline__ S load_uniform(const void *p)
-{
-    static_assert(sizeof(S) % 4 == 0, "struct size must be a multiple of 4");
-    const cptr<uint32_t> q = as_const<uint32_t>(p);
-    uint32_t w[sizeof(S) / 4];
-#pragma unroll
-    for (unsigned i = 0; i < sizeof(S) / 4; ++i) w[i] = q[i];
-    S out;
-    __builtin_memcpy(&out, w, sizeof(S));
-    return out;
 }
 
 __device__ __forceinline__ void acc_add(Acc &a, double x)

@@ -88,8 +88,9 @@ void lmm_kernel(LmmArgs a)
             if constexpr (GEN == 2) {
                 x = mc.point(a.g.seed, (uint64_t)(a.g.m_offset + m), (uint64_t)i, j);
             } else {
-                const PointCtx c = load_base(a.g.base, j);
-                x = radinv_x<GEN == 1, sizeof(T) == 8>(c, st + j, t, a.g.perm + (size_t)m * a.g.perm_stride);
+                const PointCtx c = load_base_uniform(a.g.base, j);
+                x = radinv_x<GEN == 1, sizeof(T) == 8>(c, load_uniform<StartEnt>(st + j), t,
+                                                       a.g.perm + (size_t)m * a.g.perm_stride);
             }
             w[f] = sqd * inv_normal(x, T(0));
         }

@@ -37,9 +37,35 @@
 // butterfly), one partial row per path block: deterministic.
 #pragma once
 
+#include <type_traits>
+
 #include "rq_device.h"
 
 namespace rq {
+
+// r = the first K entries of a table row (scalar loads: the row address is
+// uniform)
+template <typename T, int K> __device__ __forceinline__ void load_row(T (&r)[K], cptr<T> q)
+{
+#pragma unroll
+    for (int e = 0; e < K; ++e) r[e] = q[e];
+}
+
+// "no loads to issue" for the forward-step bodies below (their scheduling is
+// then left alone)
+struct NoPre {
+    __device__ void operator()() const {}
+};
+
+// p, made to depend on the scalar value dep: loads through the result issue
+// only once dep (the current row's first entry used) has arrived, so the wait
+// for the current row does not also wait for the next one
+template <typename T> __device__ __forceinline__ cptr<T> after(cptr<T> p, T dep)
+{
+    uint64_t u = (uint64_t)p;
+    asm volatile("" : "+s"(u) : "s"(dep));
+    return (cptr<T>)u;
+}
 
 template <typename T> __device__ __forceinline__ T adj_exp2(T x);
 template <> __device__ __forceinline__ float adj_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -94,16 +120,20 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             if constexpr (MC) {
                 x = mc.point(a.g.seed, (uint64_t)(a.g.m_offset + m), (uint64_t)i, j);
             } else {
-                const PointCtx c = load_base(a.g.base, j);
-                x = a.g.perm_on ? radinv_x<true, !kF32>(c, st + j, t, a.g.perm + (size_t)m * a.g.perm_stride)
-                                : radinv_x<false, !kF32>(c, st + j, t, a.g.perm);
+                const PointCtx c = load_base_uniform(a.g.base, j);
+                const StartEnt se = load_uniform<StartEnt>(st + j);
+                x = a.g.perm_on ? radinv_x<true, !kF32>(c, se, t, a.g.perm + (size_t)m * a.g.perm_stride)
+                                : radinv_x<false, !kF32>(c, se, t, a.g.perm);
             }
             w[f] = sqd * inv_normal(x, T(0));
         }
-        // one forward-step; on = 0 leaves a dead forward and w unchanged
-        auto body = [&](int n, T on) __attribute__((always_inline)) {
+        // one forward-step; with MASKED, on = 0 leaves a dead forward and w
+        // unchanged
+        auto body = [&](int n, T on, auto masked) __attribute__((always_inline)) {
+            constexpr bool MASKED = decltype(masked)::value;
             const cptr<T> q = tab + n * kAdjRow;
-            const T g = G(X[n] + q[7]) * on;
+            T g = G(X[n] + q[7]);
+            if constexpr (MASKED) g *= on;
 #pragma unroll
             for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
             // the (small) increment log2(e) (c_n + a_n . w) is formed first and
@@ -111,24 +141,38 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             T e = ffma(q[0], w[0], q[6]);
 #pragma unroll
             for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
-            X[n] = ffma(e, on, X[n]);
+            X[n] = MASKED ? ffma(e, on, X[n]) : X[n] + e;
         };
         const unsigned alive = (unsigned)(nf - k);
         if constexpr (kF32) {
+            // groups of kGrp forwards: the one holding forward k (n0 < k <
+            // n0 + kGrp) runs masked and first, the wholly alive ones (k <= n0
+            // < n_fwd) unmasked after it (two passes over the groups keep the
+            // two forms out of one branch)
 #pragma unroll
             for (int gq = 0; gq < NFC / kGrp; ++gq) {
                 const int n0 = gq * kGrp;
-                if ((unsigned)(n0 + kGrp - 1 - k) < (unsigned)(nf + kGrp - 1 - k)) {   // k - 3 <= n0 < nf
+                if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {
 #pragma unroll
                     for (int u = 0; u < kGrp; ++u)
-                        body(n0 + u, __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                         (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)));
+                        body(n0 + u,
+                             __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                 (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
+                             std::true_type{});
+                }
+            }
+#pragma unroll
+            for (int gq = 0; gq < NFC / kGrp; ++gq) {
+                const int n0 = gq * kGrp;
+                if ((unsigned)(n0 - k) < alive) {
+#pragma unroll
+                    for (int u = 0; u < kGrp; ++u) body(n0 + u, T(1), std::false_type{});
                 }
             }
         } else {
 #pragma unroll
             for (int n = 0; n < NFC; ++n)
-                if ((unsigned)(n - k) < alive) body(n, T(1));
+                if ((unsigned)(n - k) < alive) body(n, T(1), std::false_type{});
         }
         if constexpr (GREEKS) {
 #pragma unroll
@@ -241,44 +285,103 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         // on = 0 leaves everything unchanged
         // (a_n = sigma_n b_n, so a_n . w = sigma_n b_n . w and
         // delta a_n . Wbar = sigma_n delta b_n . Wbar: two dot products serve
-        // the state, the vega and the drift-factor adjoint)
-        auto body = [&](int n, T on) __attribute__((always_inline)) {
-            const cptr<T> q = tab + n * kAdjRow;
+        // the state, the vega and the drift-factor adjoint).  q is the
+        // forward's table row and vb its vega entry so far.  pre() runs right
+        // after the row's first use, once the wave has waited for the row: it
+        // issues the next forward's row and vega loads and stores the previous
+        // forward-step's vega entry, so that the one wait per forward-step
+        // finds all three long done.
+        T pend = T(0);   // the previous unmasked forward-step's new vega entry, not yet stored
+        const int nfk = opaque_u(nf);   // tests on it stay inside the step loop
+        auto body = [&](int n, const auto &q, T vb, T on, auto masked, auto pre) __attribute__((always_inline)) {
+            constexpr bool MASKED = decltype(masked)::value;
             T bw = q[9] * w[0];                       // log2(e) b_n . w_n
 #pragma unroll
             for (int f = 1; f < D; ++f) bw = ffma(q[9 + f], w[f], bw);
-            const T y = ffma(-ffma(q[8], bw, q[6]), on, X[n]);
+            if constexpr (!std::is_same<decltype(pre), NoPre>::value) {
+                __builtin_amdgcn_sched_barrier(0);
+                pre();
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const T y = MASKED ? ffma(-ffma(q[8], bw, q[6]), on, X[n]) : ffma(-q[8], bw, X[n] - q[6]);
             X[n] = y;
             const T g = G(y + q[7]);
-            const T ge = g * on;
-            const T xb = Xb[n] * on;
+            const T ge = MASKED ? g * on : g;
+            const T xb = MASKED ? Xb[n] * on : Xb[n];
 #pragma unroll
             for (int f = 0; f < D; ++f) Wb[f] = ffma(xb, q[f], Wb[f]);
             T dbw = q[12] * Wb[0];                    // delta b_n . Wbar
 #pragma unroll
             for (int f = 1; f < D; ++f) dbw = ffma(q[12 + f], Wb[f], dbw);
             const T h = ge * dbw;
-            vbar[n][lane] += ffma(xb, bw - q[15], h);
+            const T vnew = vb + ffma(xb, bw - q[15], h);
+            if constexpr (MASKED || std::is_same<decltype(pre), NoPre>::value)
+                vbar[n][lane] = vnew;
+            else
+                pend = vnew;   // written by the next forward-step, after its wait
             Xb[n] = ffma(q[8] * h, ffma(-kLn2, g, kLn2), Xb[n]);
 #pragma unroll
             for (int f = 0; f < D; ++f) w[f] = ffma(-ge, q[3 + f], w[f]);
         };
+        const NoPre none;
         const unsigned alive = (unsigned)(nf - k);
         if constexpr (kF32) {
+            // wholly alive groups first (unmasked), the group holding forward k
+            // last (masked), as in the forward pass but in reverse order.  The
+            // live groups' rows and vega entries are software-pipelined: rr and
+            // vo hold the next forward's.
+            T rr[kAdjRow] = {};
+            T vo = T(0);
 #pragma unroll
             for (int gq = NFC / kGrp - 1; gq >= 0; --gq) {
                 const int n0 = gq * kGrp;
-                if ((unsigned)(n0 + kGrp - 1 - k) < (unsigned)(nf + kGrp - 1 - k)) {   // k - 3 <= n0 < nf
+                if ((unsigned)(n0 - k) < alive) {                           // k <= n0 < n_fwd
+                    if (n0 + kGrp >= nfk) {                                 // highest live group
+                        load_row(rr, tab + (n0 + kGrp - 1) * kAdjRow);
+                        vo = vbar[n0 + kGrp - 1][lane];
+                    }
+#pragma unroll
+                    for (int u = kGrp - 1; u >= 0; --u) {
+                        const int n = n0 + u;
+                        T q[kAdjRow];
+#pragma unroll
+                        for (int e = 0; e < kAdjRow; ++e) q[e] = rr[e];
+                        const T vb = vo;
+                        body(n, q, vb, T(1), std::false_type{}, [&] {
+                            const cptr<T> t2 = after(tab, q[9]);
+                            __builtin_amdgcn_sched_barrier(0);
+                            if (n > 0) {
+                                load_row(rr, t2 + (n - 1) * kAdjRow);
+                                vo = vbar[n - 1][lane];
+                            }
+                            // the previous forward-step (n + 1) ran unless this is
+                            // the highest live group's first
+                            if (n + 1 < NFC && (u < kGrp - 1 || n0 + kGrp < nfk)) vbar[n + 1][lane] = pend;
+                        });
+                    }
+                }
+            }
+            {   // the last unmasked forward-step's entry: forward n = k rounded up to kGrp
+                const int nl = (k + kGrp - 1) & ~(kGrp - 1);
+                if (nl < nf) vbar[nl][lane] = pend;
+            }
+#pragma unroll
+            for (int gq = NFC / kGrp - 1; gq >= 0; --gq) {
+                const int n0 = gq * kGrp;
+                if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {        // n0 < k < n0 + kGrp
 #pragma unroll
                     for (int u = kGrp - 1; u >= 0; --u)
-                        body(n0 + u, __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                         (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)));
+                        body(n0 + u, tab + (n0 + u) * kAdjRow, vbar[n0 + u][lane],
+                             __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                 (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
+                             std::true_type{}, none);
                 }
             }
         } else {
 #pragma unroll
             for (int n = NFC - 1; n >= 0; --n)
-                if ((unsigned)(n - k) < alive) body(n, T(1));
+                if ((unsigned)(n - k) < alive)
+                    body(n, tab + n * kAdjRow, vbar[n][lane], T(1), std::false_type{}, none);
         }
     }
 

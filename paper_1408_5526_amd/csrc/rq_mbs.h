@@ -45,8 +45,9 @@ __device__ __forceinline__ void mbs_path(const MbsArgs &a, const StartEnt *__res
         if (a.g.mc) {
             x = mc.point(a.g.seed, (uint64_t)(a.g.m_offset + m), (uint64_t)i, j);
         } else {
-            const PointCtx c = load_base(a.g.base, j);
-            x = radinv_x<PERM, sizeof(T) == 8>(c, st + j, t, a.g.perm + (size_t)m * a.g.perm_stride);
+            const PointCtx c = load_base_uniform(a.g.base, j);
+            x = radinv_x<PERM, sizeof(T) == 8>(c, load_uniform<StartEnt>(st + j), t,
+                                               a.g.perm + (size_t)m * a.g.perm_stride);
         }
         const T z = inv_normal(x, T(0));
         const double onei = 1.0 + (double)ir;

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void sequence_kernel(SeqGeom g, int64_t tiles_
             continue;
         }
         const PointCtx c = load_base(g.base, j);
-        const double R = radinv_R<PERM>(c, st + j, t0 + ip, g.perm + (size_t)m * g.perm_stride);
+        const double R = radinv_R<PERM>(c, st[j], t0 + ip, g.perm + (size_t)m * g.perm_stride);
         if (DIGITS)
             ((uint64_t *)out)[obase + e] = (uint64_t)R;
         else
