@@ -110,6 +110,40 @@ def cpu_baseline(model, N: int, seed: int, m_per_core: int):
                       f"({m_per_core} per thread), FP64, {dt:.1f} s"}
 
 
+def generator_leg(rq, torch, dev, steps: int):
+    """Halton point generation alone on the GPU (the counter-based form, one
+    thread per number, written to HBM as FP64): numbers per second for the
+    random-start sequence with and without random digit permutations
+    (Rasrap), 240 dimensions.  Context for the paper's generator tables."""
+    s, n, m = 240, 1 << 16, 16
+    out = {"s": s, "N": n, "M": m}
+    for name, flags in (("random_start", 0), ("rasrap", rq.PERM_RANDOM)):
+        buf = torch.empty((m, n, s), dtype=torch.float64, device=dev)
+        ws = torch.empty(rq.sequence_workspace(s, n, m, flags), dtype=torch.uint8, device=dev)
+        _, kms, _ = _time_steps(lambda: rq.sequence(s, n, m, 5, flags, device=dev, out=buf, ws=ws), steps, 1)
+        out[name + "_gnumbers_per_s"] = s * n * m / (kms / 1e3) / 1e9
+        out[name + "_kernel_ms"] = kms
+        del buf, ws
+    out["note"] = ("FP64 digit expansion per number, 8 B written per number; the pricing kernels "
+                   "generate the same points in registers and never store them")
+    return out
+
+
+def cpu_generator_baseline():
+    """The oracle's recursive generator (Algorithm 2, exact integer partial
+    sums, one thread) on consecutive indices of the first 240 bases."""
+    import numpy as np
+    import oracle as O
+    count, n0, total = 1 << 18, 123456789, 0
+    t0 = time.perf_counter()
+    for j in range(240):
+        p = O.nth_prime(j)
+        total += O.alg2_run(p, n0 % (p ** 4), count).size
+    dt = time.perf_counter() - t0
+    return {"value": total / dt / 1e9, "unit": "GNumbers/s", "cores": 1, "kind": "oracle",
+            "sample": f"Algorithm 2, {count} consecutive terms in each of 240 bases, {dt:.2f} s"}
+
+
 def batch_leg(rq, I, torch, dev, n_cap: int, m_cap: int, steps: int):
     """The 256-instrument batch (FP32 prices + Greeks) in one persistent
     launch: whole-batch paths/s and the per-instrument completion times
@@ -154,6 +188,8 @@ def main(argv=None):
     ap.add_argument("--cpu-m-per-core", type=int, default=4)
     ap.add_argument("--batch", default="capped", choices=["capped", "full", "off"],
                     help="256-instrument batch leg: N <= 2^14 and M <= 64 (capped), as drawn (full), or none")
+    ap.add_argument("--no-generators", dest="generators", action="store_false",
+                    help="skip the point-generation leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
@@ -259,8 +295,12 @@ def main(argv=None):
     if args.batch != "off":
         caps = (1 << 14, 64) if args.batch == "capped" else (0, 0)
         line["batch"] = batch_leg(rq, I, torch, dev, caps[0], caps[1], 3)
+    if args.generators:
+        line["generators"] = generator_leg(rq, torch, dev, 3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(model, N, seed, args.cpu_m_per_core)
+        if args.generators:
+            line["generators"]["cpu_recursive"] = cpu_generator_baseline()
     print(json.dumps(line), flush=True)
     return 0
 
