@@ -40,6 +40,10 @@ FLOPS_PER_PATH_LMM80 = 93_040
 # the drift-factor adjoint and its derivative, the vega terms and rewinding
 # w (37); and the adjoint of the 80 payoffs (20 each).
 FLOPS_PER_PATH_LMM80_GREEKS = 93_040 + 3_240 * 48 + 80 * 20
+# The adjoint runs as two kernels: the forward passes (no payoffs) and the
+# payoffs with the reverse sweep.
+FLOPS_PER_PATH_LMM80_FWD = 93_040 - 80 * 12
+FLOPS_PER_PATH_LMM80_REV = 80 * 12 + 3_240 * 48 + 80 * 20
 N_GREEKS_LMM80 = 2 * 80 + 1
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 
@@ -95,6 +99,7 @@ def _time_steps(fn, steps: int, warmup: int):
     torch.cuda.synchronize()
     kernel_ms, n = rq.timer_end()
     total_ms = start.elapsed_time(stop)
+    _time_steps.parts = (rq.timer_part(1), rq.timer_part(2))   # adjoint halves: (ms, launches)
     return total_ms / steps, kernel_ms / max(n, 1), last
 
 
@@ -230,6 +235,7 @@ def main(argv=None):
     ms_g, kms_g, res_g = _time_steps(
         lambda: rq.price_caplets(model, N, M, seed, precision="fp32", greeks=True, device=dev, ws=wsg),
         args.steps, args.warmup)
+    (fwd_ms, fwd_n), (rev_ms, rev_n) = _time_steps.parts
     # 2) prices only, FP32 and the plain FP64 form, same points
     head = args.precision
     ms, kms, res = _time_steps(step(head), args.steps, args.warmup)
@@ -268,8 +274,13 @@ def main(argv=None):
         "traffic": _traffic_bytes("lmm80_3f_fp32_traffic.txt", PRICE_SOURCES)}
 
     dtype = "f32"
-    achieved = FLOPS_PER_PATH_LMM80_GREEKS * N * M / (kms_g / 1e3) / 1e12
     peak = PEAK_TFLOPS[dtype]
+    # the dominant kernel is the reverse half; its launches cover equal
+    # chunks of the N M paths, so flops per launch / mean launch time is the
+    # whole count over the summed launch times
+    paths_timed = N * M * args.steps
+    achieved = FLOPS_PER_PATH_LMM80_REV * paths_timed / (rev_ms / 1e3) / 1e12
+    achieved_fwd = FLOPS_PER_PATH_LMM80_FWD * paths_timed / (fwd_ms / 1e3) / 1e12
     line = {
         "metric": "RQMC paths/s + Greeks/s (LMM 80-fwd caplets) vs plain FP64, at equal std err",
         "value": N * M / (ms_g / 1e3),
@@ -288,8 +299,18 @@ def main(argv=None):
         "greeks_per_s": N * M * N_GREEKS_LMM80 / (ms_g / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": _traffic_bytes("lmm80_3f_fp32_greeks_traffic.txt", ADJ_SOURCES),
-                     "kernel": "lmm_adjoint_kernel<80,3,float,false>", "kernel_ms": kms_g},
+                     "traffic": _traffic_bytes("lmm80_3f_fp32_greeks_rev_traffic.txt", ADJ_SOURCES),
+                     "kernel": "lmm_adj_rev_kernel<80,3,float,false>", "kernel_ms": rev_ms / max(rev_n, 1),
+                     "launches_per_step": rev_n / args.steps,
+                     "flops_per_path": FLOPS_PER_PATH_LMM80_REV},
+        "roofline_fwd": {"bound": "alu", "achieved": achieved_fwd, "peak": peak, "unit": "TFLOP/s",
+                         "frac": achieved_fwd / peak,
+                         "traffic": _traffic_bytes("lmm80_3f_fp32_greeks_fwd_traffic.txt", ADJ_SOURCES),
+                         "kernel": "lmm_adj_fwd_kernel<80,3,float,false>", "kernel_ms": fwd_ms / max(fwd_n, 1),
+                         "launches_per_step": fwd_n / args.steps,
+                         "flops_per_path": FLOPS_PER_PATH_LMM80_FWD},
+        "adjoint_pass": {"kernel_ms": kms_g, "flops_per_path": FLOPS_PER_PATH_LMM80_GREEKS,
+                         "achieved": FLOPS_PER_PATH_LMM80_GREEKS * N * M / (kms_g / 1e3) / 1e12},
     }
     line.update(out_extra)
     if args.batch != "off":

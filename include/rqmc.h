@@ -192,9 +192,12 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
  *   prec      RQ_FP64: all path arithmetic in FP64.  RQ_FP32: forwards,
  *             drifts and normals in FP32; digits, points, numeraire,
  *             payoffs and all reductions stay FP64.
- * With grad != NULL the prices come from the adjoint kernel's forward pass
- * (same scheme; it keeps its state in log2 units, so FP64 prices agree
- * with the pricing kernel's to rounding). */
+ * With grad != NULL the prices come from the adjoint's forward pass (same
+ * scheme; it keeps its state in log2 units, so FP64 prices agree with the
+ * pricing kernel's to rounding).  The adjoint runs as two kernels over
+ * chunks of 64-path blocks: the forward passes store every step's w and the
+ * final states in the workspace (at most 16 GiB, sized by
+ * rq_caplets_workspace), then the payoffs and reverse sweeps read them. */
 rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t seed,
                            int64_t m_offset, int flags, rq_precision prec,
                            const rq_result *out, const rq_result *grad, double *per_path,
@@ -306,14 +309,23 @@ rq_status rq_lmm_pca_loadings(int n_fwd, int n_factors, double delta, double bet
 
 /* Kernel timing instrumentation.  Between rq_timer_begin and rq_timer_end
  * every entry point records a pair of HIP events on its stream around its
- * main path kernel (the LIBOR or MBS pricing kernel, or the sequence
- * kernel), for the first max_launches calls of the process; setup, copies
+ * main path kernels (the LIBOR or MBS pricing kernel, the two adjoint
+ * kernels over all their chunks, or the sequence kernel), for the first
+ * max_launches calls of the process; setup, copies
  * and reductions are outside the pair.  rq_timer_end waits for the recorded
  * events and returns the summed kernel time (ms) and the number of timed
  * launches.  Process-wide; not meant for concurrent use from several
  * threads. */
 rq_status rq_timer_begin(int max_launches);
 rq_status rq_timer_end(double *total_ms, int *n_launches);
+
+/* After rq_timer_end: the summed time (ms) and launch count of one half of
+ * the two-kernel adjoint behind rq_price_caplets with Greeks, part 1 the
+ * forward kernel (forward passes, storing w and the final states), part 2
+ * the reverse kernel (payoffs, reverse sweeps), over the same calls.  Both
+ * are 0 when no such call was timed.
+ * Errors: RQ_EINVAL for part outside {1, 2} or while the timer runs. */
+rq_status rq_timer_part(int part, double *total_ms, int *n_launches);
 
 /* Thread-local message describing the last non-OK status ("" if none). */
 const char *rq_last_error(void);

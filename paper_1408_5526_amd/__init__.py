@@ -120,6 +120,8 @@ def lib():
     L.rq_timer_begin.argtypes = [C.c_int]
     L.rq_timer_end.restype = C.c_int
     L.rq_timer_end.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.rq_timer_part.restype = C.c_int
+    L.rq_timer_part.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     _lib = L
     return L
 
@@ -529,6 +531,15 @@ def timer_end():
     ms = C.c_double(0.0)
     n = C.c_int(0)
     _check(lib().rq_timer_end(C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def timer_part(part: int):
+    """After timer_end: (ms, launches) of the adjoint's forward (part 1) or
+    reverse (part 2) kernel over the timed calls."""
+    ms = C.c_double(0.0)
+    n = C.c_int(0)
+    _check(lib().rq_timer_part(part, C.byref(ms), C.byref(n)))
     return ms.value, n.value
 
 

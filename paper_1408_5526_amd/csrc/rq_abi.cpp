@@ -40,22 +40,31 @@ rq_status fail(rq_status st, const char *fmt, ...)
     } while (0)
 
 // Optional kernel timer (rq_timer_begin / rq_timer_end).
+// Tag 0 brackets an entry point's whole main path (what rq_timer_end
+// reports); tags 1 and 2 bracket the forward and reverse halves of the
+// two-kernel adjoint inside it (rq_timer_part).
+constexpr int kTimerTags = 3;
+constexpr int kTimerPairsPerLaunch = 33;
 struct KernelTimer {
     std::mutex mu;
     bool on = false;
     std::vector<hipEvent_t> ev;   // pairs
+    std::vector<int> tag;         // per pair
     size_t used = 0;
+    double part_ms[kTimerTags] = {};
+    int part_n[kTimerTags] = {};
 } g_timer;
 
 struct TimedRegion {
     hipStream_t st;
     hipEvent_t stop = nullptr;
-    explicit TimedRegion(hipStream_t s) : st(s)
+    explicit TimedRegion(hipStream_t s, int tag = 0) : st(s)
     {
         std::lock_guard<std::mutex> lk(g_timer.mu);
         if (g_timer.on && 2 * (g_timer.used + 1) <= g_timer.ev.size()) {
             hipEventRecord(g_timer.ev[2 * g_timer.used], st);
             stop = g_timer.ev[2 * g_timer.used + 1];
+            g_timer.tag[g_timer.used] = tag;
             ++g_timer.used;
         }
     }
@@ -910,7 +919,8 @@ rq_status rq_timer_begin(int max_launches)
     if (max_launches < 1 || max_launches > 100000) return fail(RQ_EINVAL, "max_launches out of range");
     std::lock_guard<std::mutex> lk(g_timer.mu);
     if (g_timer.on) return fail(RQ_EINVAL, "timer already running");
-    g_timer.ev.assign(2 * (size_t)max_launches, nullptr);
+    g_timer.ev.assign(2 * (size_t)max_launches * kTimerPairsPerLaunch, nullptr);
+    g_timer.tag.assign((size_t)max_launches * kTimerPairsPerLaunch, 0);
     for (auto &e : g_timer.ev) {
         hipError_t h = hipEventCreate(&e);
         if (h != hipSuccess) {
@@ -929,20 +939,34 @@ rq_status rq_timer_end(double *total_ms, int *n_launches)
     std::lock_guard<std::mutex> lk(g_timer.mu);
     if (!g_timer.on) return fail(RQ_EINVAL, "timer not running");
     g_timer.on = false;
-    double tot = 0.0;
     rq_status st = RQ_OK;
+    for (int t = 0; t < kTimerTags; ++t) {
+        g_timer.part_ms[t] = 0.0;
+        g_timer.part_n[t] = 0;
+    }
     for (size_t q = 0; q < g_timer.used; ++q) {
         float ms = 0.0f;
         hipError_t h = hipEventSynchronize(g_timer.ev[2 * q + 1]);
         if (h == hipSuccess) h = hipEventElapsedTime(&ms, g_timer.ev[2 * q], g_timer.ev[2 * q + 1]);
         if (h != hipSuccess && st == RQ_OK) st = fail(RQ_EHIP, "event timing failed: %s", hipGetErrorString(h));
-        tot += ms;
+        g_timer.part_ms[g_timer.tag[q]] += ms;
+        ++g_timer.part_n[g_timer.tag[q]];
     }
     for (auto &e : g_timer.ev) hipEventDestroy(e);
     g_timer.ev.clear();
-    if (total_ms) *total_ms = tot;
-    if (n_launches) *n_launches = (int)g_timer.used;
+    if (total_ms) *total_ms = g_timer.part_ms[0];
+    if (n_launches) *n_launches = g_timer.part_n[0];
     return st;
+}
+
+rq_status rq_timer_part(int part, double *total_ms, int *n_launches)
+{
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    if (part < 1 || part >= kTimerTags) return fail(RQ_EINVAL, "part must be 1 or 2");
+    if (g_timer.on) return fail(RQ_EINVAL, "timer still running");
+    if (total_ms) *total_ms = g_timer.part_ms[part];
+    if (n_launches) *n_launches = g_timer.part_n[part];
+    return RQ_OK;
 }
 
 size_t rq_sequence_workspace(int s, int64_t N, int M, int flags)
@@ -974,11 +998,33 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
     return RQ_OK;
 }
 
-// Model-region bytes and partial-region bytes of a LIBOR call.
-// Adjoint: persistent grid size and the byte offset of its stored-w slots
-// inside the partial region.
-static int adj_slots(int64_t tasks) { return (int)std::min<int64_t>(tasks, rq::kAdjSlots); }
+// Single-call adjoint: per 64-path task, the stored step-final w
+// ([n_fwd][d][64]) and final states ([NFC][64], NFC = n_fwd rounded up to 16)
+// in elements; the store region holds a chunk of tasks, at most
+// kAdjStoreBytes in FP64 (FP32 chunks are twice as many tasks).
+static size_t adj_w_elems(const rq_lmm_model *model)
+{
+    return (size_t)model->n_fwd * model->n_factors * rq::kAdjBlockHost;
+}
+static size_t adj_task_elems(const rq_lmm_model *model)
+{
+    const int nfc = (model->n_fwd + 15) / 16 * 16;
+    return adj_w_elems(model) + (size_t)nfc * rq::kAdjBlockHost;
+}
+static size_t adj_store_bytes(const rq_lmm_model *model, int64_t tasks)
+{
+    const size_t per = adj_task_elems(model) * sizeof(double);
+    return (size_t)std::min<int64_t>(tasks, (int64_t)(rq::kAdjStoreBytes / per)) * per;
+}
+static int64_t adj_chunk(const rq_lmm_model *model, int64_t tasks, size_t elem)
+{
+    const int64_t fit = std::max<int64_t>(1, (int64_t)(adj_store_bytes(model, tasks) / (adj_task_elems(model) * elem)));
+    const int64_t n_chunks = (tasks + fit - 1) / fit;
+    return (tasks + n_chunks - 1) / n_chunks;   // equal chunks, the last one at most as large
+}
 
+// Model-region bytes and partial-region bytes of a LIBOR call; with Greeks
+// the byte offset of the adjoint's store region inside the partial region.
 static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greeks, size_t &mb, size_t &pb,
                          int &n_blk, size_t *wtop_off = nullptr)
 {
@@ -991,9 +1037,7 @@ static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greek
         n_blk = adj_blocks(N);
         pb = al((size_t)M * n_blk * (n_out + n_g) * sizeof(double));
         if (wtop_off) *wtop_off = pb;
-        // room for FP64 slots: [slots][n_fwd][d][64]
-        pb += (size_t)adj_slots((int64_t)M * n_blk) * model->n_fwd * model->n_factors * rq::kAdjBlockHost *
-              sizeof(double);
+        pb += adj_store_bytes(model, (int64_t)M * n_blk) + 256;   // + room to align the state rows
     } else {
         n_blk = lmm_blocks(N);
         pb = (size_t)M * n_blk * n_out * sizeof(double);
@@ -1057,8 +1101,14 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     a.fwd = reinterpret_cast<const double *>(w + L.model);
     a.fwd32 = reinterpret_cast<const float *>(w + L.model + (size_t)lmm_rows(model->n_fwd) * rq::kFwdRow * sizeof(double));
     a.adj = greeks ? (const void *)(w + L.model + adj_off) : nullptr;
+    const int64_t tasks = (int64_t)M * n_blk;
+    const size_t elem = prec == RQ_FP32 ? sizeof(float) : sizeof(double);
+    const int64_t chunk = greeks ? adj_chunk(model, tasks, elem) : 0;
     a.wtop = greeks ? (void *)(w + L.partial + wtop_off) : nullptr;
-    a.n_slots = greeks ? adj_slots((int64_t)M * n_blk) : 0;
+    a.xs = greeks ? (void *)(w + L.partial + wtop_off + al((size_t)chunk * adj_w_elems(model) * elem)) : nullptr;
+    a.n_slots = 0;
+    a.task0 = 0;
+    a.chunk = chunk;
     a.partial = reinterpret_cast<double *>(w + L.partial);
     a.partial_g = greeks ? a.partial + (size_t)M * n_blk * n_out : nullptr;
     a.n_g = n_g;
@@ -1072,8 +1122,23 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     a.euler = (flags & RQ_LMM_EULER) ? 1 : 0;
     {
         TimedRegion tr(st);
-        if (greeks) RQ_HIP(rq::launch_lmm_adjoint(a, model->n_factors, prec == RQ_FP32, st));
-        else RQ_HIP(rq::launch_lmm(a, model->n_factors, prec == RQ_FP32, st));
+        if (greeks) {
+            // chunks of tasks: the forward halves, then the reverse halves
+            for (int64_t t0 = 0; t0 < tasks; t0 += chunk) {
+                a.task0 = t0;
+                a.chunk = std::min<int64_t>(chunk, tasks - t0);
+                {
+                    TimedRegion tf(st, 1);
+                    RQ_HIP(rq::launch_lmm_adjoint(a, model->n_factors, prec == RQ_FP32, 1, st));
+                }
+                {
+                    TimedRegion tv(st, 2);
+                    RQ_HIP(rq::launch_lmm_adjoint(a, model->n_factors, prec == RQ_FP32, 2, st));
+                }
+            }
+        } else {
+            RQ_HIP(rq::launch_lmm(a, model->n_factors, prec == RQ_FP32, st));
+        }
     }
     if ((stt = finish(out, a.partial, n_out, 0, M, n_blk, n_out, N, st))) return stt;
     if (greeks) return finish(grad, a.partial_g, n_g, 0, M, n_blk, n_g, N, st);

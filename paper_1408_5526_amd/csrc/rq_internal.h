@@ -115,8 +115,12 @@ struct LmmArgs {
     const double *fwd;       // [n_fwd][kFwdRow]
     const float *fwd32;      // [n_fwd][kRow32]
     const void *adj;         // [n_fwd][kAdjRow] (FP32 or FP64) or nullptr
-    void *wtop;              // adjoint: [n_slots][n_fwd][d][64] step-final w, kernel precision
-    int n_slots;             // adjoint: blocks of the persistent grid
+    void *wtop;              // adjoint: step-final w, kernel precision: batch [n_slots][n_fwd][d][64],
+                             // single call [chunk][n_fwd][d][64]
+    int n_slots;             // batch adjoint: blocks of the persistent grid
+    void *xs;                // single-call adjoint: [chunk][NFC][64] final states (log2 units)
+    int64_t task0;           // single-call adjoint: first task (m n_blk + blk) of this launch
+    int64_t chunk;           // single-call adjoint: tasks of this launch
     double *partial_g;       // [M][n_blk][n_g] Greek partial sums or nullptr
     int n_g;                 // 2 n_fwd + 1
     double *partial;         // [M][n_blk][n_out]
@@ -169,9 +173,14 @@ hipError_t launch_setup(const SetupArgs &a, hipStream_t st);
 hipError_t launch_perm(const PermArgs &a, hipStream_t st);
 hipError_t launch_sequence(const SeqGeom &g, int flags, void *out, hipStream_t st);
 hipError_t launch_lmm(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
-hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, hipStream_t st);
+// part 1: forward halves of tasks [task0, task0 + chunk), storing w and the
+// final states; part 2: their payoffs and reverse sweeps
+hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, int part, hipStream_t st);
 constexpr int kAdjBlockHost = 64;    // paths per block of the adjoint kernel (one wave)
-constexpr int kAdjSlots = 2048;      // adjoint grid: 256 CUs x 8 resident waves
+constexpr int kAdjSlots = 2048;      // batch adjoint grid: 256 CUs x 8 resident waves
+// Single-call adjoint: bytes of stored w and final states per launch pair,
+// at most (the tasks are processed in chunks that fit).
+constexpr size_t kAdjStoreBytes = (size_t)16 << 30;
 hipError_t launch_mbs(const MbsArgs &a, int fp32, hipStream_t st);   // n_part == 2: tangent
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);

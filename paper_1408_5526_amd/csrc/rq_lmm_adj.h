@@ -80,9 +80,16 @@ template <> __device__ __forceinline__ double adj_rcp<double>(double x) { return
 // uniforms from Philox instead of the Halton replication (a separate
 // instantiation, so the Halton form carries no pseudo-random code).  wt is the lane's entry of
 // the block's stored-w slot; vbar the block's LDS rows.
-template <int NFC, int D, typename T, bool GREEKS, bool MC>
+// PART selects the whole task (kTaskWhole: forward, payoffs, reverse) or one
+// of its two halves for the two-kernel form: kTaskFwd runs the forward pass
+// and stores the final states at xs ([n][lane], n < NFC); kTaskRev loads them
+// and runs the payoffs and the reverse sweep.  The halves do exactly the
+// arithmetic of the whole task.
+constexpr int kTaskWhole = 0, kTaskFwd = 1, kTaskRev = 2;
+
+template <int NFC, int D, typename T, bool GREEKS, bool MC, int PART = kTaskWhole>
 __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64_t task, T *__restrict__ wt,
-                                         T (&vbar)[NFC][kWave])
+                                         T (&vbar)[NFC][kWave], T *__restrict__ xs = nullptr)
 {
     static_assert(NFC % 16 == 0 && NFC % kGrp == 0, "capacity must be a multiple of 16");
     constexpr bool kF32 = sizeof(T) == 4;
@@ -106,12 +113,12 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 
     T X[NFC], Xb[NFC];
 #pragma unroll
-    for (int n = 0; n < NFC; ++n) X[n] = T(0);
+    for (int n = 0; n < NFC; ++n) X[n] = PART == kTaskRev ? xs[n * kWave] : T(0);
 
     // ---- forward pass ----
     McPath mc;
 #pragma unroll 1
-    for (int k = 0; k < nf; ++k) {
+    for (int k = 0; k < (PART == kTaskRev ? 0 : nf); ++k) {
         T w[D];
 #pragma unroll
         for (int f = 0; f < D; ++f) {
@@ -178,6 +185,12 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll
             for (int f = 0; f < D; ++f) wt[(size_t)(k * D + f) * kWave] = w[f];
         }
+    }
+
+    if constexpr (PART == kTaskFwd) {
+#pragma unroll
+        for (int n = 0; n < NFC; ++n) xs[n * kWave] = X[n];
+        return;
     }
 
     // ---- payoffs and their adjoint (FP64) ----
@@ -410,57 +423,84 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     }
 }
 
+// Single-call adjoint, two kernels per chunk of tasks (task = m n_blk + blk,
+// one 64-path wave per block, one block per task):
+//  * lmm_adj_fwd_kernel runs the forward passes.  Its state is the 80
+//    forwards and w only, so it runs at four waves per SIMD in FP32 (the
+//    point generation and the forward-steps hide each other's latencies);
+//    it stores w per step and the final states, 82 KB per task in FP32.
+//  * lmm_adj_rev_kernel loads the final states and runs the payoffs and the
+//    reverse sweep with the vega rows in LDS, at two waves per SIMD (X and
+//    Xbar in registers).
+template <int NFC, int D, typename T, bool MC>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+void lmm_adj_fwd_kernel(LmmArgs a)
+{
+    __shared__ T vbar[NFC][kWave];   // not touched by the forward half
+    const int64_t local = blockIdx.x;
+    const int64_t task = a.task0 + local;
+    const int m = (int)(task / a.n_blk);
+    const int blk = (int)(task - (int64_t)m * a.n_blk);
+    T *wt = (T *)a.wtop + local * ((int64_t)a.n_fwd * D * kWave) + threadIdx.x;
+    T *xs = (T *)a.xs + local * ((int64_t)NFC * kWave) + threadIdx.x;
+    lmm_task<NFC, D, T, true, MC, kTaskFwd>(a, m, blk, task, wt, vbar, xs);
+}
+
 // FP32: the compiler is asked for two waves per SIMD (at most 256 registers);
 // the few values it then spills are outside the time loops.
 template <int NFC, int D, typename T, bool MC>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
-void lmm_adjoint_kernel(LmmArgs a)
+void lmm_adj_rev_kernel(LmmArgs a)
 {
     __shared__ T vbar[NFC][kWave];
-    // this block's slot of stored step-final w: [k][f][lane]
-    T *wt = (T *)a.wtop + (size_t)blockIdx.x * ((size_t)a.n_fwd * D * kWave) + threadIdx.x;
-    const int64_t tasks = (int64_t)a.g.M * a.n_blk;
-#pragma unroll 1
-    for (int64_t task = blockIdx.x; task < tasks; task += gridDim.x) {
-        const int m = (int)(task / a.n_blk);
-        const int blk = (int)(task - (int64_t)m * a.n_blk);
-        lmm_task<NFC, D, T, true, MC>(a, m, blk, task, wt, vbar);
-    }
+    const int64_t local = blockIdx.x;
+    const int64_t task = a.task0 + local;
+    const int m = (int)(task / a.n_blk);
+    const int blk = (int)(task - (int64_t)m * a.n_blk);
+    T *wt = (T *)a.wtop + local * ((int64_t)a.n_fwd * D * kWave) + threadIdx.x;
+    T *xs = (T *)a.xs + local * ((int64_t)NFC * kWave) + threadIdx.x;
+    lmm_task<NFC, D, T, true, MC, kTaskRev>(a, m, blk, task, wt, vbar, xs);
 }
 
+// One half (part kTaskFwd or kTaskRev) over tasks [a.task0, a.task0 +
+// a.chunk).  The host launches the forward half, then the reverse half of
+// the same tasks on the same stream, so the stored values are complete.
 template <int NFC, int D, typename T, bool MC>
-static hipError_t launch_adj_t(const LmmArgs &a, hipStream_t st)
+static hipError_t launch_adj_t(const LmmArgs &a, int part, hipStream_t st)
 {
-    hipLaunchKernelGGL((lmm_adjoint_kernel<NFC, D, T, MC>), dim3((unsigned)a.n_slots), dim3(kWave), 0, st, a);
+    if (part == kTaskFwd)
+        hipLaunchKernelGGL((lmm_adj_fwd_kernel<NFC, D, T, MC>), dim3((unsigned)a.chunk), dim3(kWave), 0, st, a);
+    else
+        hipLaunchKernelGGL((lmm_adj_rev_kernel<NFC, D, T, MC>), dim3((unsigned)a.chunk), dim3(kWave), 0, st, a);
     return hipGetLastError();
 }
 
 template <int D, typename T, bool MC>
-static hipError_t launch_adj_d(const LmmArgs &a, hipStream_t st)
+static hipError_t launch_adj_d(const LmmArgs &a, int part, hipStream_t st)
 {
-    if (a.n_fwd <= 16) return launch_adj_t<16, D, T, MC>(a, st);
-    if (a.n_fwd <= 32) return launch_adj_t<32, D, T, MC>(a, st);
-    if (a.n_fwd <= 48) return launch_adj_t<48, D, T, MC>(a, st);
-    if (a.n_fwd <= 64) return launch_adj_t<64, D, T, MC>(a, st);
-    return launch_adj_t<80, D, T, MC>(a, st);
+    if (a.n_fwd <= 16) return launch_adj_t<16, D, T, MC>(a, part, st);
+    if (a.n_fwd <= 32) return launch_adj_t<32, D, T, MC>(a, part, st);
+    if (a.n_fwd <= 48) return launch_adj_t<48, D, T, MC>(a, part, st);
+    if (a.n_fwd <= 64) return launch_adj_t<64, D, T, MC>(a, part, st);
+    return launch_adj_t<80, D, T, MC>(a, part, st);
 }
 
 // Adjoint launch for one precision and point generator (instantiated in
 // rq_lmm_adj{32,64}{,mc}.hip, so that the four compile in parallel).
 template <typename T, bool MC>
-static hipError_t launch_adj_prec(const LmmArgs &a, int n_factors, hipStream_t st)
+static hipError_t launch_adj_prec(const LmmArgs &a, int n_factors, int part, hipStream_t st)
 {
     switch (n_factors) {
-    case 1: return launch_adj_d<1, T, MC>(a, st);
-    case 2: return launch_adj_d<2, T, MC>(a, st);
-    case 3: return launch_adj_d<3, T, MC>(a, st);
+    case 1: return launch_adj_d<1, T, MC>(a, part, st);
+    case 2: return launch_adj_d<2, T, MC>(a, part, st);
+    case 3: return launch_adj_d<3, T, MC>(a, part, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_lmm_adjoint_f32(const LmmArgs &a, int n_factors, hipStream_t st);
-hipError_t launch_lmm_adjoint_f64(const LmmArgs &a, int n_factors, hipStream_t st);
-hipError_t launch_lmm_adjoint_f32mc(const LmmArgs &a, int n_factors, hipStream_t st);
-hipError_t launch_lmm_adjoint_f64mc(const LmmArgs &a, int n_factors, hipStream_t st);
+hipError_t launch_lmm_adjoint_f32(const LmmArgs &a, int n_factors, int part, hipStream_t st);
+hipError_t launch_lmm_adjoint_f64(const LmmArgs &a, int n_factors, int part, hipStream_t st);
+hipError_t launch_lmm_adjoint_f32mc(const LmmArgs &a, int n_factors, int part, hipStream_t st);
+hipError_t launch_lmm_adjoint_f64mc(const LmmArgs &a, int n_factors, int part, hipStream_t st);
 
 }  // namespace rq

@@ -3,9 +3,9 @@
 
 namespace rq {
 
-hipError_t launch_lmm_adjoint_f64mc(const LmmArgs &a, int n_factors, hipStream_t st)
+hipError_t launch_lmm_adjoint_f64mc(const LmmArgs &a, int n_factors, int part, hipStream_t st)
 {
-    return launch_adj_prec<double, true>(a, n_factors, st);
+    return launch_adj_prec<double, true>(a, n_factors, part, st);
 }
 
 }  // namespace rq
