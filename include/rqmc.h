@@ -203,6 +203,14 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
                            const rq_result *out, const rq_result *grad, double *per_path,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* The adjoint's store region (see rq_price_caplets): at most `bytes` per
+ * chunk, counted in FP64 (at least one 64-path task per chunk); 0 restores
+ * the default, 16 GiB.  Process-wide; it changes the workspace size that
+ * rq_caplets_workspace reports for calls with Greeks and the number of
+ * kernel launches, never the results (each task's arithmetic and partial
+ * row are the same in any chunk).  Set it before sizing the workspace. */
+rq_status rq_set_adjoint_store_limit(size_t bytes);
+
 /* price_mbs(params, N, M): present value of the mortgage pool.
  *   grad  NULL, or the pathwise total derivative dPV/di0 (one output per
  *         replication; rates scale with i0 and the payment c and the

@@ -120,6 +120,8 @@ def lib():
     L.rq_timer_begin.argtypes = [C.c_int]
     L.rq_timer_end.restype = C.c_int
     L.rq_timer_end.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.rq_set_adjoint_store_limit.restype = C.c_int
+    L.rq_set_adjoint_store_limit.argtypes = [C.c_size_t]
     L.rq_timer_part.restype = C.c_int
     L.rq_timer_part.argtypes = [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)]
     _lib = L
@@ -532,6 +534,13 @@ def timer_end():
     n = C.c_int(0)
     _check(lib().rq_timer_end(C.byref(ms), C.byref(n)))
     return ms.value, n.value
+
+
+def set_adjoint_store_limit(nbytes: int) -> None:
+    """Bytes (FP64-counted) of the two-kernel adjoint's store region per
+    chunk of tasks; 0 restores the default (16 GiB).  Results never depend
+    on it; the workspace size does."""
+    _check(lib().rq_set_adjoint_store_limit(nbytes))
 
 
 def timer_part(part: int):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1011,10 +1012,13 @@ static size_t adj_task_elems(const rq_lmm_model *model)
     const int nfc = (model->n_fwd + 15) / 16 * 16;
     return adj_w_elems(model) + (size_t)nfc * rq::kAdjBlockHost;
 }
+static std::atomic<size_t> g_adj_store_limit{rq::kAdjStoreBytes};
+
 static size_t adj_store_bytes(const rq_lmm_model *model, int64_t tasks)
 {
     const size_t per = adj_task_elems(model) * sizeof(double);
-    return (size_t)std::min<int64_t>(tasks, (int64_t)(rq::kAdjStoreBytes / per)) * per;
+    const int64_t fit = std::max<int64_t>(1, (int64_t)(g_adj_store_limit.load() / per));
+    return (size_t)std::min<int64_t>(tasks, fit) * per;
 }
 static int64_t adj_chunk(const rq_lmm_model *model, int64_t tasks, size_t elem)
 {
@@ -1042,6 +1046,12 @@ static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greek
         n_blk = lmm_blocks(N);
         pb = (size_t)M * n_blk * n_out * sizeof(double);
     }
+}
+
+rq_status rq_set_adjoint_store_limit(size_t bytes)
+{
+    g_adj_store_limit.store(bytes ? bytes : rq::kAdjStoreBytes);
+    return RQ_OK;
 }
 
 size_t rq_caplets_workspace(const rq_lmm_model *model, int64_t N, int M, int flags, rq_precision prec,

@@ -74,6 +74,27 @@ def test_caplet_argument_errors_return_before_launch():
         rq.lib().rq_caplets_workspace(C.byref(h.c), 4096, 4, 0, 1, 0)
 
 
+def test_adjoint_store_limit_sizes_the_workspace():
+    # the two-kernel adjoint stores w and the final states for one chunk of
+    # 64-path tasks: (20 x 3 + 32) x 64 x 8 B = 47,104 B per task counted in
+    # FP64; a limit of 7 tasks shrinks the Greeks workspace accordingly, and
+    # 0 restores the default (16 GiB, i.e. all 64 tasks here)
+    m = I.lmm_curve80(20, 3)
+    h = rq._LmmHost(m)
+    per = (20 * 3 + 32) * 64 * 8
+    full = rq.lib().rq_caplets_workspace(C.byref(h.c), 4096, 1, 0, 1, 1)
+    try:
+        rq.set_adjoint_store_limit(7 * per)
+        small = rq.lib().rq_caplets_workspace(C.byref(h.c), 4096, 1, 0, 1, 1)
+        rq.set_adjoint_store_limit(1)          # below one task: still one task
+        one = rq.lib().rq_caplets_workspace(C.byref(h.c), 4096, 1, 0, 1, 1)
+    finally:
+        rq.set_adjoint_store_limit(0)
+    assert full - small == (64 - 7) * per
+    assert small - one == 6 * per
+    assert rq.lib().rq_caplets_workspace(C.byref(h.c), 4096, 1, 0, 1, 1) == full
+
+
 def test_mbs_argument_errors_return_before_launch():
     p = rq._mbs_c(I.MbsParams(0, 0.007, 0.02, 0.01, -0.005, 10, 0.5))
     res = rq.rq_result(1, 0, 0, 0)

@@ -120,9 +120,27 @@ def test_caplet_adjoint_zero_vol_closed_form():
     assert np.allclose(g, fd, rtol=1e-7, atol=1e-10 * np.abs(fd).max())
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_caplet_adjoint_chunks_do_not_change_results(precision):
+    # 3 replications x 16 blocks = 48 tasks; a store limit of 7 FP64 tasks
+    # gives 7 chunks in FP64 (6 of 7 tasks, the last of 6) and 4 in FP32 (12
+    # each): prices and Greeks bit-identical to the single-chunk call
+    m = I.lmm_curve80(20, 3)
+    _say("adjoint chunks", precision)
+    ref = rq.price_caplets(m, 1000, 3, 7, flags=rq.PERM_RANDOM, precision=precision, greeks=True)
+    try:
+        rq.set_adjoint_store_limit(7 * (20 * 3 + 32) * 64 * 8)
+        got = rq.price_caplets(m, 1000, 3, 7, flags=rq.PERM_RANDOM, precision=precision, greeks=True)
+    finally:
+        rq.set_adjoint_store_limit(0)
+    for a, b in ((got.theta, ref.theta), (got.greeks.theta, ref.greeks.theta)):
+        assert np.array_equal(_np(a).view(np.uint64), _np(b).view(np.uint64))
+
+
 def test_caplet_adjoint_full_size_greeks_run():
-    # the 80-forward book with Greeks, FP32, at N = 2^16, M = 256: finite,
-    # deterministic, and the sampled replication matches the FP64 adjoint
+    # the 80-forward book with Greeks, FP32, at N = 2^16, M = 256 (two chunks
+    # of 131,072 tasks): finite, and the sampled replication matches the FP64
+    # adjoint of that replication alone
     c = I.cfg4()[0]
     _say("adjoint full", c.N, c.M)
     r = rq.price_caplets(c.model, c.N, c.M, c.seed, precision="fp32", greeks=True)
