@@ -103,6 +103,17 @@ def _time_steps(fn, steps: int, warmup: int):
     return total_ms / steps, kernel_ms / max(n, 1), last
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(model, N: int, seed: int, m_per_core: int):
     import oracle as O
     cores = O.num_threads()
@@ -110,9 +121,17 @@ def cpu_baseline(model, N: int, seed: int, m_per_core: int):
     t0 = time.perf_counter()
     O.price_caplets(model, N, m_sub, seed)
     dt = time.perf_counter() - t0
+    # the same oracle on one core (2 replications)
+    O.set_num_threads(1)
+    t1 = time.perf_counter()
+    O.price_caplets(model, N, 2, seed)
+    dt1 = time.perf_counter() - t1
+    O.set_num_threads(cores)
     return {"value": m_sub * N / dt, "unit": "paths/s", "cores": cores, "kind": "oracle",
             "sample": f"{m_sub} of the 1024 replications at full N = {N} "
-                      f"({m_per_core} per thread), FP64, {dt:.1f} s"}
+                      f"({m_per_core} per thread), FP64, {dt:.1f} s",
+            "value_1core": 2 * N / dt1, "sample_1core": f"2 replications at N = {N} on one thread, {dt1:.1f} s",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
 def generator_leg(rq, torch, dev, steps: int):
@@ -297,6 +316,7 @@ def main(argv=None):
         "config": {"workload": "lmm80_3f_caplet_book_greeks", "n_fwd": 80, "n_factors": 3, "s": 240,
                    "N": N, "M": M, "seed": seed, "precision": "fp32", "greeks": N_GREEKS_LMM80},
         "greeks_per_s": N * M * N_GREEKS_LMM80 / (ms_g / 1e3),
+        "greeks_per_s_lmm160": N * M * (N_GREEKS_LMM80 - 1) / (ms_g / 1e3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": _traffic_bytes("lmm80_3f_fp32_greeks_rev_traffic.txt", ADJ_SOURCES),

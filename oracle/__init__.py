@@ -95,6 +95,8 @@ def _load():
     lib.orc_alg2_run.argtypes = [C.c_uint64, _ip, C.c_uint64, C.c_int64, _u64p]
     lib.orc_num_threads.restype = C.c_int
     lib.orc_num_threads.argtypes = []
+    lib.orc_set_num_threads.restype = None
+    lib.orc_set_num_threads.argtypes = [C.c_int]
     _lib = lib
     return lib
 
@@ -109,6 +111,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls (timing only)."""
+    _load().orc_set_num_threads(n)
 
 
 # -- generator primitives --------------------------------------------------

@@ -673,6 +673,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads for the following calls (timing on one core or on all). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* Batched helpers for the test-suite (same arithmetic as above). */
 void orc_ppnd16_vec(int64_t n, const double *u, double *z)
