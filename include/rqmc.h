@@ -180,7 +180,7 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
 
 /* price_caplets(model, N, M): caplets and book of the LIBOR market model.
  *   out       results with n_out = n_fwd + 1
- *   grad      NULL, or pathwise Greeks of the book from the adjoint kernel,
+ *   grad      NULL, or pathwise Greeks of the book from the adjoint kernels,
  *             n_g = 2 n_fwd + 1 outputs per replication: [0, n_fwd)
  *             dbook/dL_n(0) for n = 1..n_fwd (strikes held fixed); [n_fwd]
  *             dbook/dL_0(0) (the spot rate, through the numeraire);

@@ -176,7 +176,7 @@ hipError_t launch_lmm(const LmmArgs &a, int n_factors, int fp32, hipStream_t st)
 // part 1: forward halves of tasks [task0, task0 + chunk), storing w and the
 // final states; part 2: their payoffs and reverse sweeps
 hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, int part, hipStream_t st);
-constexpr int kAdjBlockHost = 64;    // paths per block of the adjoint kernel (one wave)
+constexpr int kAdjBlockHost = 64;    // paths per block (task) of the adjoint kernels (one wave)
 constexpr int kAdjSlots = 2048;      // batch adjoint grid: 256 CUs x 8 resident waves
 // Single-call adjoint: bytes of stored w and final states per launch pair,
 // at most (the tasks are processed in chunks that fit).

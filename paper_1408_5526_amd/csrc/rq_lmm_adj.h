@@ -6,7 +6,7 @@
 //     g_n = G(X_n) = 1 / (1 + 2^{-(X_n + l_n)}),  l_n = log2(delta L_n(0))
 //     w  += g_n delta a_n                       (w is now w_n)
 //     X_n += log2(e) (c_n + a_n . w_n)
-//   and the lane stores the step's final w (d numbers) in its block's slot.
+//   and the lane stores the step's final w (d numbers).
 // Payoffs (FP64): L_n(T_n) = L_n(0) 2^{X_n}; P_n = delta (L_n - K_n)^+ / num_{n+1},
 //   num_{n+1} = num_0 prod_{j<=n} (1 + delta L_j(T_j)); book = sum_n P_n.
 //
@@ -28,12 +28,13 @@
 // (one rounding of the increment per step, as in the forward pass).
 //
 // Per path: n_fwd+1 prices (caplets, book) and 2 n_fwd + 1 Greeks (deltas,
-// spot delta, vegas).  A block is one wave of 64 paths; the grid is
-// persistent (a fixed number of blocks strides over the replications' path
-// blocks), so the per-block slot for the stored w is bounded by the grid, not
-// by N M.  State and adjoint state live in registers, the vega accumulators
-// in LDS ([forward][lane], conflict-free; before the sweep the same rows
-// hold the payoff adjoint).  Outputs are wave sums (transpose
+// spot delta, vegas).  A task is one wave of 64 paths.  A single call runs
+// the forward halves of a chunk of tasks in one kernel (storing w and the
+// final states per task) and their payoffs and reverse sweeps in a second;
+// the batch runs whole tasks in its persistent kernel, with a stored-w slot
+// per block.  State and adjoint state live in registers, the vega
+// accumulators in LDS ([forward][lane], conflict-free; before the sweep the
+// same rows hold the payoff adjoint).  Outputs are wave sums (transpose
 // butterfly), one partial row per path block: deterministic.
 #pragma once
 

@@ -1,4 +1,4 @@
-// rq_lmm_adj32.hip -- FP32 instantiations of the LIBOR adjoint kernel.
+// rq_lmm_adj32.hip -- FP32 instantiations of the LIBOR adjoint kernels (forward and reverse halves).
 #include "rq_lmm_adj.h"
 
 namespace rq {

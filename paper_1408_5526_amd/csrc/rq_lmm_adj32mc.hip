@@ -1,4 +1,4 @@
-// rq_lmm_adj32mc.hip -- FP32 instantiations of the LIBOR adjoint kernel for pseudo-random (Philox) points.
+// rq_lmm_adj32mc.hip -- FP32 instantiations of the LIBOR adjoint kernels for pseudo-random (Philox) points.
 #include "rq_lmm_adj.h"
 
 namespace rq {

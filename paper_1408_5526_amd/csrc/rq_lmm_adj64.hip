@@ -1,4 +1,4 @@
-// rq_lmm_adj64.hip -- FP64 instantiations of the LIBOR adjoint kernel and the dispatch.
+// rq_lmm_adj64.hip -- FP64 instantiations of the LIBOR adjoint kernels and the dispatch.
 #include "rq_lmm_adj.h"
 
 namespace rq {

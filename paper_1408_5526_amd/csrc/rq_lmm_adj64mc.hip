@@ -1,4 +1,4 @@
-// rq_lmm_adj64mc.hip -- FP64 instantiations of the LIBOR adjoint kernel for pseudo-random (Philox) points.
+// rq_lmm_adj64mc.hip -- FP64 instantiations of the LIBOR adjoint kernels for pseudo-random (Philox) points.
 #include "rq_lmm_adj.h"
 
 namespace rq {
