@@ -168,6 +168,36 @@ def cpu_generator_baseline():
             "sample": f"Algorithm 2, {count} consecutive terms in each of 240 bases, {dt:.2f} s"}
 
 
+def mbs_leg(rq, I, torch, dev, steps: int):
+    """The 360-month MBS pool (s = 360, N = 2^14, M = 64): paths/s in FP64 and
+    FP32, and the paper's efficiency (sample sd of the estimates x time) of
+    the Halton replications against Philox points."""
+    c = I.cfg2()
+    out = {"workload": "mbs360_N2^14_M64", "N": c.N, "M": c.M}
+    ws = torch.empty(rq.mbs_workspace(c.model, c.N, c.M, 0, "fp64"), dtype=torch.uint8, device=dev)
+    for name, prec, flags in (("fp64", "fp64", 0), ("fp32", "fp32", 0), ("fp32_philox", "fp32", rq.MC_PHILOX)):
+        ms, kms, r = _time_steps(lambda: rq.price_mbs(c.model, c.N, c.M, c.seed, flags=flags, precision=prec,
+                                                      device=dev, ws=ws), steps, 1)
+        sd = r.sd[0].item()
+        out[name] = {"paths_per_s": c.N * c.M / (ms / 1e3), "ms_per_step": ms, "kernel_ms": kms,
+                     "pv": r.mean[0].item(), "sd": sd, "efficiency_sd_x_s": sd * ms / 1e3}
+    return out
+
+
+def cpu_mbs_baseline():
+    """The oracle on the same MBS workload, a bounded sample of replications."""
+    import oracle as O
+    import rqmc_inputs as I
+    c = I.cfg2()
+    cores = O.num_threads()
+    m_sub = min(c.M, 4 * cores)
+    t0 = time.perf_counter()
+    O.price_mbs(c.model, c.N, m_sub, c.seed)
+    dt = time.perf_counter() - t0
+    return {"value": m_sub * c.N / dt, "unit": "paths/s", "cores": cores, "kind": "oracle",
+            "sample": f"{m_sub} of the {c.M} replications at full N = {c.N}, FP64, {dt:.1f} s"}
+
+
 def batch_leg(rq, I, torch, dev, n_cap: int, m_cap: int, steps: int):
     """The 256-instrument batch (FP32 prices + Greeks) in one persistent
     launch: whole-batch paths/s and the per-instrument completion times
@@ -214,6 +244,7 @@ def main(argv=None):
                     help="256-instrument batch leg: N <= 2^14 and M <= 64 (capped), as drawn (full), or none")
     ap.add_argument("--no-generators", dest="generators", action="store_false",
                     help="skip the point-generation leg")
+    ap.add_argument("--no-mbs", dest="mbs", action="store_false", help="skip the MBS leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB mebibytes device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
@@ -287,6 +318,10 @@ def main(argv=None):
         "paths_per_s": N * M / (ms_mc / 1e3), "kernel_ms": kms_mc,
         "book_rq": res_mc.mean[-1].item(), "book_se": res_mc.se[-1].item(),
         "se_ratio_mc_over_rqmc": res_mc.se[-1].item() / res.se[-1].item()}
+    # the paper's efficiency: sample sd of the M estimates x execution time
+    # (lower is better), book price, FP32 prices only
+    out_extra["efficiency_sd_x_s"] = {"rqmc_halton": res.sd[-1].item() * ms / 1e3,
+                                      "mc_philox": res_mc.sd[-1].item() * ms_mc / 1e3}
     out_extra["prices_only_fp32"] = {
         "paths_per_s": N * M / (ms / 1e3), "ms_per_step": ms, "kernel_ms": kms,
         "achieved_tflops": FLOPS_PER_PATH_LMM80 * N * M / (kms / 1e3) / 1e12,
@@ -338,10 +373,14 @@ def main(argv=None):
         line["batch"] = batch_leg(rq, I, torch, dev, caps[0], caps[1], 3)
     if args.generators:
         line["generators"] = generator_leg(rq, torch, dev, 3)
+    if args.mbs:
+        line["mbs"] = mbs_leg(rq, I, torch, dev, 3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(model, N, seed, args.cpu_m_per_core)
         if args.generators:
             line["generators"]["cpu_recursive"] = cpu_generator_baseline()
+        if args.mbs:
+            line["mbs"]["cpu_baseline"] = cpu_mbs_baseline()
     print(json.dumps(line), flush=True)
     return 0
 
