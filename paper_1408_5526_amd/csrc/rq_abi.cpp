@@ -41,6 +41,10 @@ rq_status fail(rq_status st, const char *fmt, ...)
     } while (0)
 
 // Optional kernel timer (rq_timer_begin / rq_timer_end).
+// The adjoint's store region per chunk (single calls) or window (batch),
+// FP64-counted (rq_set_adjoint_store_limit).
+std::atomic<size_t> g_adj_store_limit{rq::kAdjStoreBytes};
+
 // Tag 0 brackets an entry point's whole main path (what rq_timer_end
 // reports); tags 1 and 2 bracket the forward and reverse halves of the
 // two-kernel adjoint inside it (rq_timer_part).
@@ -571,7 +575,7 @@ struct BatchPlan {
     int n_red = 0;              // reduce / finalize entries
     size_t o_inst = 0, o_item0 = 0, o_setup = 0, o_setup_pf = 0, o_red = 0, o_red_pf = 0, o_fin = 0,
            o_fin_pf = 0, o_queue = 0;
-    size_t host_bytes = 0, o_wtop = 0, wtop_bytes = 0, total = 0;
+    size_t host_bytes = 0, o_store = 0, store_bytes = 0, total = 0;
     int64_t n_items = 0, setup_total = 0, red_blocks = 0;
     bool any_lmm = false;
 };
@@ -681,10 +685,16 @@ rq_status plan_batch(const rq_instrument *inst, int n_inst, rq_precision prec, b
         bp.setup_total += p.setup_units;
         bp.red_blocks += (int64_t)p.M * (greeks ? 2 : 1);
     }
-    bp.wtop_bytes = (greeks && bp.any_lmm)
-                        ? (size_t)rq::kBatchMaxSlots * rq::kBatchSlotElems * (prec == RQ_FP32 ? 4 : 8)
-                        : 0;
-    bp.o_wtop = take(bp.wtop_bytes);
+    // Greeks: the window store, one slot per item of a window, FP64-counted
+    // so that the size does not depend on the precision (FP32 windows hold
+    // twice the items)
+    bp.store_bytes = 0;
+    if (greeks && bp.any_lmm) {
+        const size_t per = (size_t)rq::kBatchItemElems * sizeof(double);
+        const int64_t fit = std::max<int64_t>(1, (int64_t)(g_adj_store_limit.load() / per));
+        bp.store_bytes = (size_t)std::min<int64_t>(bp.n_items, fit) * per;
+    }
+    bp.o_store = take(bp.store_bytes);
     bp.total = o;
     return RQ_OK;
 }
@@ -722,17 +732,33 @@ rq_status run_batch(const rq_instrument *inst, int n_inst, rq_precision prec, bo
     const bool f32 = prec == RQ_FP32;
     const int cus = device_cus();
     if (cus <= 0) return fail(RQ_EHIP, "cannot query the device's compute units");
-    int per_cu = tu.waves_per_cu;
-    if (per_cu == 0) per_cu = rq::batch_blocks_per_cu(f32, greeks);
-    if (per_cu <= 0) return fail(RQ_EHIP, "occupancy query of the batch kernel failed");
-    int64_t grid = (int64_t)cus * per_cu;
-    if (greeks && bp.any_lmm && grid > rq::kBatchMaxSlots) grid = rq::kBatchMaxSlots;
-    if (grid > bp.n_items) grid = bp.n_items;
-    int chunk = tu.chunk;
-    if (chunk == 0) {   // about 16 grabs per block, at most 8 items a grab
-        const int64_t c = bp.n_items / (grid * 16);
-        chunk = (int)std::max<int64_t>(1, std::min<int64_t>(8, c));
+    // launches: without Greeks one (phase 0) over all items; with Greeks,
+    // per window of items, phase 1 (LIBOR forward halves, MBS items) and, if
+    // any LIBOR item, phase 2 (LIBOR reverse halves)
+    const size_t elem = f32 ? sizeof(float) : sizeof(double);
+    const int64_t window = (greeks && bp.any_lmm)
+                               ? std::max<int64_t>(1, (int64_t)(bp.store_bytes / ((size_t)rq::kBatchItemElems * elem)))
+                               : bp.n_items;
+    std::vector<int> phases;
+    if (!greeks) phases = {0};
+    else if (bp.any_lmm) phases = {1, 2};
+    else phases = {1};
+    // blocks per CU: the tuning's value holds for the two-wave kernels
+    // (phase 2, or phase 0); phase 1 runs twice as many where it fits
+    int occ_of[3] = {0, 0, 0};
+    for (int ph : phases) {
+        occ_of[ph] = rq::batch_blocks_per_cu(f32, greeks, ph);
+        if (occ_of[ph] <= 0) return fail(RQ_EHIP, "occupancy query of the batch kernel failed");
     }
+    auto grid_of = [&](int ph, int64_t n_win) {
+        int per_cu = occ_of[ph];
+        if (tu.waves_per_cu > 0) per_cu = std::min(per_cu, tu.waves_per_cu * (ph == 1 ? 2 : 1));
+        return std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, n_win));
+    };
+    auto chunk_of = [&](int64_t grid, int64_t n_win) {
+        if (tu.chunk > 0) return tu.chunk;   // else about 16 grabs per block, at most 8 items a grab
+        return (int)std::max<int64_t>(1, std::min<int64_t>(8, n_win / (grid * 16)));
+    };
 
     uint8_t *w = (uint8_t *)ws;
     std::vector<uint8_t> host(bp.host_bytes, 0);
@@ -784,7 +810,10 @@ rq_status run_batch(const rq_instrument *inst, int n_inst, rq_precision prec, bo
             a.fwd = reinterpret_cast<const double *>(w + p.o_model);
             a.fwd32 = reinterpret_cast<const float *>(w + p.o_model + (size_t)lmm_rows(p.nf) * rq::kFwdRow * sizeof(double));
             a.adj = w + p.o_model + p.adj_off;
-            a.wtop = greeks ? (void *)(w + bp.o_wtop) : nullptr;
+            a.wtop = nullptr;   // the batch kernel passes each item's slot of the window store
+            a.xs = nullptr;
+            a.task0 = 0;
+            a.chunk = 0;
             a.n_slots = 0;
             a.partial = part;
             a.partial_g = greeks ? part + p.part_g : nullptr;
@@ -875,16 +904,26 @@ rq_status run_batch(const rq_instrument *inst, int n_inst, rq_precision prec, bo
     ba.inst = reinterpret_cast<const rq::BatchInst *>(w + bp.o_inst);
     ba.item0 = reinterpret_cast<const int64_t *>(w + bp.o_item0);
     ba.n_inst = n_inst;
-    ba.chunk = chunk;
+    ba.chunk = 1;
     ba.n_items = items;
     ba.queue = queue;
     ba.t_first = reinterpret_cast<unsigned long long *>(t_first);
     ba.t_last = reinterpret_cast<unsigned long long *>(t_last);
     ba.n_caller = n_inst;
-    ba.wtop = greeks ? (void *)(w + bp.o_wtop) : nullptr;
+    ba.store = bp.store_bytes ? (void *)(w + bp.o_store) : nullptr;
     {
         TimedRegion tr(st);
-        RQ_HIP(rq::launch_batch(ba, (int)grid, f32, greeks, st));
+        for (int64_t w0 = 0; w0 < items; w0 += window) {
+            ba.w0 = w0;
+            ba.w1 = std::min<int64_t>(items, w0 + window);
+            for (int ph : phases) {
+                if (w0 > 0 || ph != phases[0])   // the queue restarts at the window's first item
+                    RQ_HIP(rq::launch_batch_init(queue, nullptr, nullptr, 0, st));
+                const int64_t grid = grid_of(ph, ba.w1 - ba.w0);
+                ba.chunk = chunk_of(grid, ba.w1 - ba.w0);
+                RQ_HIP(rq::launch_batch(ba, (int)grid, f32, greeks, ph, st));
+            }
+        }
     }
     rq::BatchReduce br{reinterpret_cast<const rq::ReduceArgs *>(w + bp.o_red),
                        reinterpret_cast<const int64_t *>(w + bp.o_red_pf), bp.n_red};
@@ -1012,8 +1051,6 @@ static size_t adj_task_elems(const rq_lmm_model *model)
     const int nfc = (model->n_fwd + 15) / 16 * 16;
     return adj_w_elems(model) + (size_t)nfc * rq::kAdjBlockHost;
 }
-static std::atomic<size_t> g_adj_store_limit{rq::kAdjStoreBytes};
-
 static size_t adj_store_bytes(const rq_lmm_model *model, int64_t tasks)
 {
     const size_t per = adj_task_elems(model) * sizeof(double);
@@ -1309,7 +1346,7 @@ rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision 
         rq_status s0 = plan_batch(inst, n_inst, prec, greeks, RQ_ORDER_COST, bp);
         if (s0) return s0;
     }
-    const int occ = rq::batch_blocks_per_cu(prec == RQ_FP32, greeks);
+    const int occ = rq::batch_blocks_per_cu(prec == RQ_FP32, greeks, greeks ? 2 : 0);
     if (occ <= 0) return fail(RQ_EHIP, "occupancy query of the batch kernel failed");
     std::vector<rq_tuning> cand;
     const int chunks[] = {1, 2, 4, 8};

@@ -89,16 +89,16 @@ hipError_t launch_batch_finalize(const BatchFinalize &b, int64_t total, hipStrea
 
 namespace rq {
 
-hipError_t launch_batch(const BatchArgs &b, int grid, int fp32, int greeks, hipStream_t st)
+hipError_t launch_batch(const BatchArgs &b, int grid, int fp32, int greeks, int phase, hipStream_t st)
 {
-    if (fp32) return greeks ? launch_batch_f32g(b, grid, st) : launch_batch_f32p(b, grid, st);
-    return greeks ? launch_batch_f64g(b, grid, st) : launch_batch_f64p(b, grid, st);
+    if (fp32) return greeks ? launch_batch_f32g(b, grid, phase, st) : launch_batch_f32p(b, grid, st);
+    return greeks ? launch_batch_f64g(b, grid, phase, st) : launch_batch_f64p(b, grid, st);
 }
 
-int batch_blocks_per_cu(int fp32, int greeks)
+int batch_blocks_per_cu(int fp32, int greeks, int phase)
 {
-    if (fp32) return greeks ? batch_occ_f32g() : batch_occ_f32p();
-    return greeks ? batch_occ_f64g() : batch_occ_f64p();
+    if (fp32) return greeks ? batch_occ_f32g(phase) : batch_occ_f32p();
+    return greeks ? batch_occ_f64g(phase) : batch_occ_f64p();
 }
 
 }  // namespace rq

@@ -1,10 +1,17 @@
-// rq_batch_f64g.hip -- batch kernel instance (double, Greeks: true); one
-// translation unit per instance so that they compile in parallel.
+// rq_batch_f64g.hip -- batch kernel instances (double, Greeks: the forward
+// phase and the reverse phase); one translation unit per precision so that
+// they compile in parallel.
 #include "rq_batch_kernel.h"
 
 namespace rq {
 
-hipError_t launch_batch_f64g(const BatchArgs &b, int grid, hipStream_t st) { return launch_batch_t<double, true>(b, grid, st); }
-int batch_occ_f64g() { return batch_blocks_per_cu_t<double, true>(); }
+hipError_t launch_batch_f64g(const BatchArgs &b, int grid, int phase, hipStream_t st)
+{
+    return phase == 1 ? launch_batch_t<double, true, 1>(b, grid, st) : launch_batch_t<double, true, 2>(b, grid, st);
+}
+int batch_occ_f64g(int phase)
+{
+    return phase == 1 ? batch_blocks_per_cu_t<double, true, 1>() : batch_blocks_per_cu_t<double, true, 2>();
+}
 
 }  // namespace rq

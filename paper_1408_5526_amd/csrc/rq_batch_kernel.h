@@ -3,8 +3,12 @@
 // MBS pools), in a fixed precision, with or without Greeks.
 //
 // Each block is one wave.  It takes `chunk` consecutive items at a time from
-// an atomic queue (one vector atomic by lane 0) until the queue runs dry,
-// so every wave reaches the exit.  The instrument of an item is found by a
+// an atomic queue (one vector atomic by lane 0) until the window [w0, w1)
+// of items runs dry, so every wave reaches the exit.  With Greeks a window
+// runs in two launches, as the single-call adjoint does: phase 1 the LIBOR
+// items' forward halves (storing w and the final states in the item's slot
+// of the window's store) and the whole MBS items, at four waves per SIMD in
+// FP32; phase 2 the LIBOR items' payoffs and reverse sweeps, at two.  The instrument of an item is found by a
 // binary search over item0 (wave-uniform scalar loads); its kind and factor
 // count select the path code, so all branches are wave-uniform.  LIBOR
 // items run the task of rq_lmm_adj.h at the full forward capacity (forwards
@@ -20,13 +24,14 @@
 
 namespace rq {
 
-template <typename T, bool GREEKS>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && GREEKS ? 2 : 1)))
+template <typename T, bool GREEKS, int PHASE>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 ? (PHASE == 2 ? 2 : 4) : (PHASE == 1 ? 2 : 1))))
 void batch_kernel(BatchArgs b)
 {
+    constexpr int part = PHASE == 1 ? kTaskFwd : PHASE == 2 ? kTaskRev : kTaskWhole;
     __shared__ T vbar[kMaxFwd][kWave];
     const int lane = threadIdx.x;
-    T *wt = GREEKS ? (T *)b.wtop + (size_t)blockIdx.x * kBatchSlotElems + lane : nullptr;
     const cptr<int64_t> item0 = as_const<int64_t>(b.item0);
     const cptr<BatchInst> inst = as_const<BatchInst>(b.inst);
 #pragma unroll 1
@@ -34,10 +39,10 @@ void batch_kernel(BatchArgs b)
         unsigned long long got = 0ull;
         if (lane == 0) got = atomicAdd(b.queue, (unsigned long long)b.chunk);
         // every lane is active here: the first active lane is lane 0
-        const int64_t start = (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(got >> 32)) << 32) |
-                                        (uint64_t)__builtin_amdgcn_readfirstlane((unsigned)got));
-        if (start >= b.n_items) break;
-        const int64_t end = start + b.chunk < b.n_items ? start + b.chunk : b.n_items;
+        const int64_t start = b.w0 + (int64_t)(((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(got >> 32)) << 32) |
+                                               (uint64_t)__builtin_amdgcn_readfirstlane((unsigned)got));
+        if (start >= b.w1) break;
+        const int64_t end = start + b.chunk < b.w1 ? start + b.chunk : b.w1;
 #pragma unroll 1
         for (int64_t it = start; it < end; ++it) {
             int lo = 0, hi = b.n_inst;
@@ -47,21 +52,26 @@ void batch_kernel(BatchArgs b)
                 else hi = mid;
             }
             const int64_t local = it - item0[lo];
+            const bool lmm = inst[lo].kind == kInstLmm;
+            if (PHASE == 2 && !lmm) continue;   // MBS items are done in phase 1
             const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-            if (inst[lo].kind == kInstLmm) {
+            if (lmm) {
                 const LmmArgs a = load_uniform<LmmArgs>(&b.inst[lo].lmm);
                 const int m = (int)(local / a.n_blk);
                 const int blk = (int)(local - (int64_t)m * a.n_blk);
+                T *slot = GREEKS ? (T *)b.store + (it - b.w0) * (int64_t)kBatchItemElems : nullptr;
+                T *wt = GREEKS ? slot + lane : nullptr;
+                T *xs = GREEKS ? slot + kMaxFwd * 3 * kWave + lane : nullptr;
                 const int sel = inst[lo].n_factors * 2 + (a.g.mc ? 1 : 0);
                 switch (sel) {
-                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false>(a, m, blk, local, wt, vbar); break;
-                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true>(a, m, blk, local, wt, vbar); break;
-                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false>(a, m, blk, local, wt, vbar); break;
-                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true>(a, m, blk, local, wt, vbar); break;
-                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true>(a, m, blk, local, wt, vbar); break;
-                default: lmm_task<kMaxFwd, 3, T, GREEKS, false>(a, m, blk, local, wt, vbar); break;
+                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs); break;
+                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs); break;
+                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs); break;
+                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs); break;
+                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs); break;
+                default: lmm_task<kMaxFwd, 3, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs); break;
                 }
-            } else {
+            } else if (PHASE != 2) {
                 const MbsArgs a = load_uniform<MbsArgs>(&b.inst[lo].mbs);
                 const int m = (int)(local / a.n_blk);
                 const int blk = (int)(local - (int64_t)m * a.n_blk);
@@ -77,28 +87,29 @@ void batch_kernel(BatchArgs b)
     }
 }
 
-template <typename T, bool GREEKS>
+template <typename T, bool GREEKS, int PHASE>
 static hipError_t launch_batch_t(const BatchArgs &b, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((batch_kernel<T, GREEKS>), dim3((unsigned)grid), dim3(kWave), 0, st, b);
+    hipLaunchKernelGGL((batch_kernel<T, GREEKS, PHASE>), dim3((unsigned)grid), dim3(kWave), 0, st, b);
     return hipGetLastError();
 }
 
-template <typename T, bool GREEKS>
+template <typename T, bool GREEKS, int PHASE>
 static int batch_blocks_per_cu_t()
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<T, GREEKS>, kWave, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel<T, GREEKS, PHASE>, kWave, 0) != hipSuccess)
+        return 0;
     return n;
 }
 
 hipError_t launch_batch_f32p(const BatchArgs &b, int grid, hipStream_t st);
-hipError_t launch_batch_f32g(const BatchArgs &b, int grid, hipStream_t st);
+hipError_t launch_batch_f32g(const BatchArgs &b, int grid, int phase, hipStream_t st);
 hipError_t launch_batch_f64p(const BatchArgs &b, int grid, hipStream_t st);
-hipError_t launch_batch_f64g(const BatchArgs &b, int grid, hipStream_t st);
+hipError_t launch_batch_f64g(const BatchArgs &b, int grid, int phase, hipStream_t st);
 int batch_occ_f32p();
-int batch_occ_f32g();
+int batch_occ_f32g(int phase);
 int batch_occ_f64p();
-int batch_occ_f64g();
+int batch_occ_f64g(int phase);
 
 }  // namespace rq

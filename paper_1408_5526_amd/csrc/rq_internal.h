@@ -195,8 +195,9 @@ constexpr int kMaxFwd = 80;
 // instrument k owns [item0[k], item0[k+1]).
 constexpr int kInstLmm = 0;
 constexpr int kInstMbs = 1;
-constexpr int kBatchSlotElems = kMaxFwd * 3 * kWave;   // stored-w slot, elements
-constexpr int kBatchMaxSlots = 2048;                     // blocks of a Greeks batch
+// Greeks batch: per LIBOR work item, the stored step-final w and final
+// states of its forward half ([kMaxFwd][3][64] then [kMaxFwd][64]), elements
+constexpr int kBatchItemElems = kMaxFwd * 3 * kWave + kMaxFwd * kWave;
 
 struct BatchInst {
     LmmArgs lmm;             // kind LMM: n_blk counts 64-path blocks
@@ -216,7 +217,8 @@ struct BatchArgs {
     unsigned long long *queue;                  // next free item (zeroed by batch_init)
     unsigned long long *t_first, *t_last;       // [n_caller] s_memrealtime ticks, or nullptr
     int n_caller;
-    void *wtop;              // Greeks: [grid][kBatchSlotElems] kernel precision
+    void *store;             // Greeks: [w1 - w0][kBatchItemElems] kernel precision
+    int64_t w0, w1;          // the items of this launch (a window of the execution order)
 };
 
 // Batched setup / reductions: argument arrays with an exclusive prefix of
@@ -242,9 +244,11 @@ hipError_t launch_batch_init(unsigned long long *queue, unsigned long long *t_fi
 hipError_t launch_batch_setup(const BatchSetup &b, int64_t total, hipStream_t st);
 hipError_t launch_batch_reduce(const BatchReduce &b, int64_t blocks, hipStream_t st);
 hipError_t launch_batch_finalize(const BatchFinalize &b, int64_t total, hipStream_t st);
-hipError_t launch_batch(const BatchArgs &b, int grid, int fp32, int greeks, hipStream_t st);
+// phase 0: whole items without Greeks; with Greeks phase 1 runs the LIBOR
+// items' forward halves and the MBS items, phase 2 the LIBOR reverse halves
+hipError_t launch_batch(const BatchArgs &b, int grid, int fp32, int greeks, int phase, hipStream_t st);
 // Resident blocks per CU of the batch kernel for (fp32, greeks), from the
 // occupancy calculator.
-int batch_blocks_per_cu(int fp32, int greeks);
+int batch_blocks_per_cu(int fp32, int greeks, int phase);
 
 }  // namespace rq

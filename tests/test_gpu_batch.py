@@ -9,7 +9,8 @@ Bars:
     single-instrument entry point (same per-path code, block sums in the
     same or a different fixed order) to 1e-13 relative;
   * results are bit-identical for every launch shape (chunk, blocks per CU,
-    instrument order), since each work item writes its own partial row;
+    instrument order, windows of the two-phase Greeks form), since each work
+    item writes its own partial row;
   * timestamps bracket every instrument's work.
 """
 import dataclasses
@@ -132,6 +133,25 @@ def test_batch_invariant_to_launch_shape():
                          (got.results[k].greeks.theta, ref.results[k].greeks.theta),
                          (got.results[k].se, ref.results[k].se)):
                 assert np.array_equal(_np(a).view(np.uint64), _np(b).view(np.uint64)), (tu, k)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_windows_do_not_change_results(precision):
+    # with Greeks the items run in windows (forward phase, then reverse
+    # phase); a store limit of 5 FP64 item slots makes many small windows,
+    # one of them ragged: prices and Greeks bit-identical to one window
+    batch = _mixed()
+    _say("batch windows", precision)
+    ref = rq.price_batch(batch, precision=precision, greeks=True)
+    try:
+        rq.set_adjoint_store_limit(5 * (80 * 3 + 80) * 64 * 8)
+        got = rq.price_batch(batch, precision=precision, greeks=True, tuning=(2, 1, rq.ORDER_GIVEN))
+    finally:
+        rq.set_adjoint_store_limit(0)
+    for k in range(len(batch)):
+        for a, b in ((got.results[k].theta, ref.results[k].theta),
+                     (got.results[k].greeks.theta, ref.results[k].greeks.theta)):
+            assert np.array_equal(_np(a).view(np.uint64), _np(b).view(np.uint64)), k
 
 
 def test_batch_timestamps_bracket_every_instrument():
