@@ -31,8 +31,9 @@
 // spot delta, vegas).  A task is one wave of 64 paths.  A single call runs
 // the forward halves of a chunk of tasks in one kernel (storing w and the
 // final states per task) and their payoffs and reverse sweeps in a second;
-// the batch runs whole tasks in its persistent kernel, with a stored-w slot
-// per block.  State and adjoint state live in registers, the vega
+// the batch does the same per window of its work items (and runs whole
+// tasks without Greeks for its prices).  State and adjoint state live in
+// registers, the vega
 // accumulators in LDS ([forward][lane], conflict-free; before the sweep the
 // same rows hold the payoff adjoint).  Outputs are wave sums (transpose
 // butterfly), one partial row per path block: deterministic.
@@ -80,7 +81,7 @@ template <> __device__ __forceinline__ double adj_rcp<double>(double x) { return
 // payoffs only (the batch kernel's pricing form).  MC draws the path's
 // uniforms from Philox instead of the Halton replication (a separate
 // instantiation, so the Halton form carries no pseudo-random code).  wt is the lane's entry of
-// the block's stored-w slot; vbar the block's LDS rows.
+// the task's stored-w rows ([k][f][64]); vbar the block's LDS rows.
 // PART selects the whole task (kTaskWhole: forward, payoffs, reverse) or one
 // of its two halves for the two-kernel form: kTaskFwd runs the forward pass
 // and stores the final states at xs ([n][lane], n < NFC); kTaskRev loads them
