@@ -24,9 +24,12 @@
 
 namespace rq {
 
+// Waves per SIMD asked of the compiler: FP32 phase 1 (forward halves and
+// MBS items) four, FP32 phases 0 and 2 two (their payoff and adjoint state
+// need the registers); FP64 one.
 template <typename T, bool GREEKS, int PHASE>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
-    sizeof(T) == 4 ? (PHASE == 2 ? 2 : 4) : (PHASE == 1 ? 2 : 1))))
+    sizeof(T) == 4 ? (PHASE == 1 ? 4 : 2) : 1)))
 void batch_kernel(BatchArgs b)
 {
     constexpr int part = PHASE == 1 ? kTaskFwd : PHASE == 2 ? kTaskRev : kTaskWhole;
