@@ -56,6 +56,7 @@ struct KernelTimer {
     std::vector<hipEvent_t> ev;   // pairs
     std::vector<int> tag;         // per pair
     size_t used = 0;
+    bool record_failed = false;   // a hipEventRecord failed: rq_timer_end reports it
     double part_ms[kTimerTags] = {};
     int part_n[kTimerTags] = {};
 } g_timer;
@@ -67,7 +68,7 @@ struct TimedRegion {
     {
         std::lock_guard<std::mutex> lk(g_timer.mu);
         if (g_timer.on && 2 * (g_timer.used + 1) <= g_timer.ev.size()) {
-            hipEventRecord(g_timer.ev[2 * g_timer.used], st);
+            if (hipEventRecord(g_timer.ev[2 * g_timer.used], st) != hipSuccess) g_timer.record_failed = true;
             stop = g_timer.ev[2 * g_timer.used + 1];
             g_timer.tag[g_timer.used] = tag;
             ++g_timer.used;
@@ -75,7 +76,10 @@ struct TimedRegion {
     }
     ~TimedRegion()
     {
-        if (stop) hipEventRecord(stop, st);
+        if (stop && hipEventRecord(stop, st) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_timer.mu);
+            g_timer.record_failed = true;
+        }
     }
 };
 
@@ -964,12 +968,13 @@ rq_status rq_timer_begin(int max_launches)
     for (auto &e : g_timer.ev) {
         hipError_t h = hipEventCreate(&e);
         if (h != hipSuccess) {
-            for (auto &x : g_timer.ev) if (x) hipEventDestroy(x);
+            for (auto &x : g_timer.ev) if (x) (void)hipEventDestroy(x);
             g_timer.ev.clear();
             return fail(RQ_EHIP, "hipEventCreate failed: %s", hipGetErrorString(h));
         }
     }
     g_timer.used = 0;
+    g_timer.record_failed = false;
     g_timer.on = true;
     return RQ_OK;
 }
@@ -992,8 +997,9 @@ rq_status rq_timer_end(double *total_ms, int *n_launches)
         g_timer.part_ms[g_timer.tag[q]] += ms;
         ++g_timer.part_n[g_timer.tag[q]];
     }
-    for (auto &e : g_timer.ev) hipEventDestroy(e);
+    for (auto &e : g_timer.ev) (void)hipEventDestroy(e);
     g_timer.ev.clear();
+    if (g_timer.record_failed && st == RQ_OK) st = fail(RQ_EHIP, "recording a timing event failed");
     if (total_ms) *total_ms = g_timer.part_ms[0];
     if (n_launches) *n_launches = g_timer.part_n[0];
     return st;
@@ -1359,7 +1365,7 @@ rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision 
     hipEvent_t e0, e1;
     RQ_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return fail(RQ_EHIP, "hipEventCreate failed");
     }
     double bms = INFINITY;
@@ -1385,8 +1391,8 @@ rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision 
             bt = cand[c];
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (stt != RQ_OK) return stt;
     *best = bt;
     if (best_ms) *best_ms = bms;
