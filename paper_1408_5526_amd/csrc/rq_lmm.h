@@ -36,8 +36,6 @@
 // deterministic.
 #pragma once
 
-#include <type_traits>
-
 #include "rq_device.h"
 
 namespace rq {
@@ -96,21 +94,12 @@ void lmm_kernel(LmmArgs a)
             }
             w[f] = sqd * inv_normal(x, T(0));
         }
-        // One forward-step of forward n.  FP32: on = 1 for a forward alive in
-        // this step, 0 otherwise; a dead forward's drift factor and state
-        // update are multiplied by 0, so a group of kGrp forwards runs as one
-        // branch-free block whose independent drift factors overlap with the
-        // chain through w.  Wholly dead groups are skipped.  (FP64 branches
-        // per forward and ignores `on`.)
-        // With MASKED false (a group whose forwards are all alive) the 0/1
-        // factor is left out.
-        auto body = [&](int n, T on, auto masked) __attribute__((always_inline)) {
-            constexpr bool MASKED = decltype(masked)::value;
+        // One forward-step of forward n (alive in this step).
+        auto body = [&](int n) __attribute__((always_inline)) {
             if constexpr (kF32) {
                 const float *q = a.fwd32 + n * kRow32;
                 const float s = X[n] + q[7];            // log2(delta L_n)
-                float g = __builtin_amdgcn_rcpf(1.0f + fexp2(-s));
-                if constexpr (MASKED) g *= on;
+                const float g = __builtin_amdgcn_rcpf(1.0f + fexp2(-s));
 #pragma unroll
                 for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
                 // form the (small) step increment first, then add it to the
@@ -123,12 +112,12 @@ void lmm_kernel(LmmArgs a)
 #pragma unroll
                     for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
                     const float r = fmaxf(ffma(e, 0.693147180559945309f, 1.0f), 0x1p-100f);
-                    X[n] = MASKED ? ffma(__builtin_amdgcn_logf(r), on, X[n]) : X[n] + __builtin_amdgcn_logf(r);
+                    X[n] += __builtin_amdgcn_logf(r);
                 } else {
                     float e = ffma(q[0], w[0], q[6]);
 #pragma unroll
                     for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
-                    X[n] = MASKED ? ffma(e, on, X[n]) : X[n] + e;
+                    X[n] += e;
                 }
             } else {
                 const double dl = delta * X[n];
@@ -154,22 +143,20 @@ void lmm_kernel(LmmArgs a)
             // too costly to spend on dead forwards)
 #pragma unroll
             for (int n = 0; n < NFC; ++n)
-                if ((unsigned)(n - k) < alive) body(n, 1.0, std::false_type{});
+                if ((unsigned)(n - k) < alive) body(n);
             continue;
         }
-        // FP32: the group holding forward k (n0 < k < n0 + kGrp) runs masked
-        // and first, the wholly alive groups (k <= n0 < n_fwd) unmasked after
-        // it (two passes keep the two forms out of one branch)
+        // FP32: in the group holding forward k (n0 < k < n0 + kGrp) each live
+        // forward runs behind its own uniform branch, first; the wholly alive
+        // groups (k <= n0 < n_fwd) run after it as branch-free blocks (two
+        // passes keep the two forms out of one branch)
 #pragma unroll
         for (int gq = 0; gq < NFC / kGrp; ++gq) {
             const int n0 = gq * kGrp;
             if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {
 #pragma unroll
-                for (int u = 0; u < kGrp; ++u)   // wave-uniform 0/1, formed as bits so that it stays scalar
-                    body(n0 + u,
-                         __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                             (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
-                         std::true_type{});
+                for (int u = 0; u < kGrp; ++u)   // its live forwards only, one uniform branch each
+                    if ((unsigned)(n0 + u - k) < alive) body(n0 + u);
             }
         }
 #pragma unroll
@@ -177,7 +164,7 @@ void lmm_kernel(LmmArgs a)
             const int n0 = gq * kGrp;
             if ((unsigned)(n0 - k) < alive) {
 #pragma unroll
-                for (int u = 0; u < kGrp; ++u) body(n0 + u, T(1), std::false_type{});
+                for (int u = 0; u < kGrp; ++u) body(n0 + u);
             }
         }
     }

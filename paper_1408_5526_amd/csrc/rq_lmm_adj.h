@@ -136,13 +136,10 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             }
             w[f] = sqd * inv_normal(x, T(0));
         }
-        // one forward-step; with MASKED, on = 0 leaves a dead forward and w
-        // unchanged
-        auto body = [&](int n, T on, auto masked) __attribute__((always_inline)) {
-            constexpr bool MASKED = decltype(masked)::value;
+        // one forward-step of forward n (alive in this step)
+        auto body = [&](int n) __attribute__((always_inline)) {
             const cptr<T> q = tab + n * kAdjRow;
-            T g = G(X[n] + q[7]);
-            if constexpr (MASKED) g *= on;
+            const T g = G(X[n] + q[7]);
 #pragma unroll
             for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
             // the (small) increment log2(e) (c_n + a_n . w) is formed first and
@@ -150,24 +147,21 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             T e = ffma(q[0], w[0], q[6]);
 #pragma unroll
             for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
-            X[n] = MASKED ? ffma(e, on, X[n]) : X[n] + e;
+            X[n] += e;
         };
         const unsigned alive = (unsigned)(nf - k);
         if constexpr (kF32) {
-            // groups of kGrp forwards: the one holding forward k (n0 < k <
-            // n0 + kGrp) runs masked and first, the wholly alive ones (k <= n0
-            // < n_fwd) unmasked after it (two passes over the groups keep the
-            // two forms out of one branch)
+            // groups of kGrp forwards: in the one holding forward k (n0 < k <
+            // n0 + kGrp) each live forward runs behind its own uniform branch,
+            // first; the wholly alive groups (k <= n0 < n_fwd) run after it
+            // (two passes over the groups keep the two forms out of one branch)
 #pragma unroll
             for (int gq = 0; gq < NFC / kGrp; ++gq) {
                 const int n0 = gq * kGrp;
                 if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {
 #pragma unroll
-                    for (int u = 0; u < kGrp; ++u)
-                        body(n0 + u,
-                             __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                 (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
-                             std::true_type{});
+                    for (int u = 0; u < kGrp; ++u)   // its live forwards only, one uniform branch each
+                        if ((unsigned)(n0 + u - k) < alive) body(n0 + u);
                 }
             }
 #pragma unroll
@@ -175,13 +169,13 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                 const int n0 = gq * kGrp;
                 if ((unsigned)(n0 - k) < alive) {
 #pragma unroll
-                    for (int u = 0; u < kGrp; ++u) body(n0 + u, T(1), std::false_type{});
+                    for (int u = 0; u < kGrp; ++u) body(n0 + u);
                 }
             }
         } else {
 #pragma unroll
             for (int n = 0; n < NFC; ++n)
-                if ((unsigned)(n - k) < alive) body(n, T(1), std::false_type{});
+                if ((unsigned)(n - k) < alive) body(n);
         }
         if constexpr (GREEKS) {
 #pragma unroll
@@ -385,7 +379,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                 const int n0 = gq * kGrp;
                 if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {        // n0 < k < n0 + kGrp
 #pragma unroll
-                    for (int u = kGrp - 1; u >= 0; --u)
+                    for (int u = kGrp - 1; u >= 0; --u)   // masked (branches here cost SGPRs the loop needs)
                         body(n0 + u, tab + (n0 + u) * kAdjRow, vbar[n0 + u][lane],
                              __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                                  (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
