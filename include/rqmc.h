@@ -190,8 +190,9 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
  *   per_path  optional device [M][N][n_out] FP64: every path's discounted
  *             payoffs (a verification hook; NULL in production)
  *   prec      RQ_FP64: all path arithmetic in FP64.  RQ_FP32: forwards,
- *             drifts and normals in FP32; digits, points, numeraire,
- *             payoffs and all reductions stay FP64.
+ *             drifts and normals in FP32 (the fixing value's 2^X too);
+ *             digits, points, numeraire, payoffs and all reductions stay
+ *             FP64.
  * With grad != NULL the prices come from the adjoint's forward pass (same
  * scheme; it keeps its state in log2 units, so FP64 prices agree with the
  * pricing kernel's to rounding).  The adjoint runs as two kernels over

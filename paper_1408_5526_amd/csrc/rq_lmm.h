@@ -183,7 +183,9 @@ void lmm_kernel(LmmArgs a)
                 // rows beyond n_fwd are 0 (no numeraire factor, no payoff);
                 // the caplet flag multiplies the payoff
                 const int n = c * 16 + q;
-                const double Lf = kF32 ? r64(n, 7) * exp2((double)X[n]) : (double)X[n];
+                // FP32: 2^X in FP32 (one more rounding, of the size the FP32
+                // state already carries), the fixing value and payoff in FP64
+                const double Lf = kF32 ? r64(n, 7) * (double)fexp2((float)X[n]) : (double)X[n];
                 const double onep = 1.0 + delta * Lf;
                 const double ex = Lf - r64(n, 8);
                 double pay = ex > 0.0 ? r64(n, 9) * (delta * ex / (num * onep)) : 0.0;

@@ -190,6 +190,8 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     }
 
     // ---- payoffs and their adjoint (FP64) ----
+    // (In FP32, 2^X is formed in FP32, one more rounding of the size the FP32
+    // state already carries; the fixing value, numeraire and payoffs are FP64.)
     // With Greeks, pass 1 forms the book and pass 2 (16 forwards at a time)
     // the payoffs again, their wave sums, and the adjoint of the fixing
     // values, parked in the (not yet used) vega rows of LDS so that the
@@ -215,7 +217,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int n = c * 16 + q;
-                    const double Lf = f1[n * kFwdRow + 7] * exp2((double)X[n]);
+                    const double Lf = f1[n * kFwdRow + 7] * (double)adj_exp2<T>(X[n]);
                     num *= 1.0 + delta * Lf;
                     const double ex = Lf - f1[n * kFwdRow + 8];
                     book += ex > 0.0 ? f1[n * kFwdRow + 9] * (delta * ex / num) : 0.0;
@@ -234,7 +236,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int n = c * 16 + q;
-                    const double Lf = f2[n * kFwdRow + 7] * exp2((double)X[n]);
+                    const double Lf = f2[n * kFwdRow + 7] * (double)adj_exp2<T>(X[n]);
                     const double onep = 1.0 + delta * Lf;
                     num *= onep;
                     const double rn = delta / num;
