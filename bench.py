@@ -170,17 +170,22 @@ def cpu_generator_baseline():
 
 def mbs_leg(rq, I, torch, dev, steps: int):
     """The 360-month MBS pool (s = 360, N = 2^14, M = 64): paths/s in FP64 and
-    FP32, and the paper's efficiency (sample sd of the estimates x time) of
-    the Halton replications against Philox points."""
+    FP32 (and FP32 with the pathwise dPV/di0), and the paper's efficiency
+    (sample sd of the estimates x time) of the Halton replications against
+    Philox points."""
     c = I.cfg2()
     out = {"workload": "mbs360_N2^14_M64", "N": c.N, "M": c.M}
-    ws = torch.empty(rq.mbs_workspace(c.model, c.N, c.M, 0, "fp64"), dtype=torch.uint8, device=dev)
-    for name, prec, flags in (("fp64", "fp64", 0), ("fp32", "fp32", 0), ("fp32_philox", "fp32", rq.MC_PHILOX)):
+    ws = torch.empty(rq.mbs_workspace(c.model, c.N, c.M, 0, "fp64", greeks=True), dtype=torch.uint8, device=dev)
+    for name, prec, flags, gr in (("fp64", "fp64", 0, False), ("fp32", "fp32", 0, False),
+                                  ("fp32_philox", "fp32", rq.MC_PHILOX, False), ("fp32_greeks", "fp32", 0, True)):
         ms, kms, r = _time_steps(lambda: rq.price_mbs(c.model, c.N, c.M, c.seed, flags=flags, precision=prec,
-                                                      device=dev, ws=ws), steps, 1)
+                                                      greeks=gr, device=dev, ws=ws), steps, 1)
         sd = r.sd[0].item()
         out[name] = {"paths_per_s": c.N * c.M / (ms / 1e3), "ms_per_step": ms, "kernel_ms": kms,
                      "pv": r.mean[0].item(), "sd": sd, "efficiency_sd_x_s": sd * ms / 1e3}
+        if gr:
+            out[name]["dpv_di0"] = r.greeks.mean[0].item()
+            out[name]["dpv_di0_se"] = r.greeks.se[0].item()
     return out
 
 
