@@ -915,11 +915,32 @@ rq_status run_batch(const rq_instrument *inst, int n_inst, rq_precision prec, bo
     ba.t_last = reinterpret_cast<unsigned long long *>(t_last);
     ba.n_caller = n_inst;
     ba.store = bp.store_bytes ? (void *)(w + bp.o_store) : nullptr;
+    // window cuts: whole instruments where they fit (so that an instrument's
+    // two phases run in one window), an instrument larger than a window in
+    // full windows of its own
+    std::vector<int64_t> cuts{0};
+    if (window < items) {
+        int64_t start = 0;
+        for (int e = 0; e < n_inst; ++e) {
+            const int64_t a = item0[e], b = item0[e + 1];
+            if (b - start <= window) continue;
+            if (a > start) {
+                cuts.push_back(a);
+                start = a;
+            }
+            while (b - start > window) {
+                start += window;
+                cuts.push_back(start);
+            }
+        }
+    }
+    if (cuts.back() != items) cuts.push_back(items);
     {
         TimedRegion tr(st);
-        for (int64_t w0 = 0; w0 < items; w0 += window) {
+        for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+            const int64_t w0 = cuts[c];
             ba.w0 = w0;
-            ba.w1 = std::min<int64_t>(items, w0 + window);
+            ba.w1 = cuts[c + 1];
             for (int ph : phases) {
                 if (w0 > 0 || ph != phases[0])   // the queue restarts at the window's first item
                     RQ_HIP(rq::launch_batch_init(queue, nullptr, nullptr, 0, st));
