@@ -189,6 +189,30 @@ def mbs_leg(rq, I, torch, dev, steps: int):
     return out
 
 
+def small_call_leg(rq, I, torch, dev, calls: int = 50):
+    """The small 1-factor caplet (10 forwards, s = 10, N = 4096, M = 32):
+    host-to-result latency of one call (median wall time, stream synced),
+    and the device time of its main kernel."""
+    import statistics
+    c = I.cfg1()
+    ws = torch.empty(rq.caplets_workspace(c.model, c.N, c.M, 0, "fp64"), dtype=torch.uint8, device=dev)
+    out = {"workload": "lmm10_1f_caplet_N4096_M32"}
+    for prec in ("fp32", "fp64"):
+        f = lambda: rq.price_caplets(c.model, c.N, c.M, c.seed, precision=prec, device=dev, ws=ws)
+        f()
+        torch.cuda.synchronize()
+        walls = []
+        for _ in range(calls):
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        _, kms, r = _time_steps(f, 5, 1)
+        out[prec] = {"call_us_median": statistics.median(walls) * 1e6, "kernel_us": kms * 1e3,
+                     "price": r.mean[-1].item()}
+    return out
+
+
 def cpu_mbs_baseline():
     """The oracle on the same MBS workload, a bounded sample of replications."""
     import oracle as O
@@ -380,6 +404,7 @@ def main(argv=None):
         line["generators"] = generator_leg(rq, torch, dev, 3)
     if args.mbs:
         line["mbs"] = mbs_leg(rq, I, torch, dev, 3)
+        line["small_call"] = small_call_leg(rq, I, torch, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(model, N, seed, args.cpu_m_per_core)
         if args.generators:
