@@ -58,6 +58,8 @@ def _mixed():
         Ins("mbs", I.mbs_paper(1), 1, 1, 2),
         Ins("lmm", I.lmm_curve80(24, 2), 200, 2, 12, flags=rq.MC_PHILOX),
         Ins("mbs", I.mbs_paper(120), 150, 2, 13, flags=rq.MC_PHILOX),
+        Ins("lmm", I.lmm_curve80(1, 1), 70, 2, 14),
+        Ins("lmm", I.lmm_curve80(17, 3), 129, 1, 15, m_offset=3),
     ]
 
 

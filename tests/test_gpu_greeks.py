@@ -61,6 +61,11 @@ SMOOTH = [
     ("nf33d1", lambda: I.lmm_curve80(33, 1), 256, 1, 4),
     ("nf12d2-mc", lambda: I.lmm_curve80(12, 2), 300, 2, 6, rq.MC_PHILOX),
     ("nf12d2-permrep", lambda: I.lmm_curve80(12, 2), 300, 2, 6, rq.PERM_PER_REP),
+    # edge shapes of the grouped sweeps: one forward; two forwards, two
+    # factors; one past a capacity boundary (17 -> 32); a ragged last block
+    ("nf1d1", lambda: I.lmm_curve80(1, 1), 200, 2, 11),
+    ("nf2d2", lambda: I.lmm_curve80(2, 2), 130, 2, 12),
+    ("nf17d3", lambda: I.lmm_curve80(17, 3), 333, 2, 13),
 ]
 
 
