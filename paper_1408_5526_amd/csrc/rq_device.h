@@ -317,8 +317,27 @@ __device__ __forceinline__ double wave_sum16(double (&v)[16], int lane)
         const uint32_t hi = ((uint32_t)(ua >> 32) & m) | ((uint32_t)(ub >> 32) & ~m);
         return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
     };
+    // The first two levels (partners 32 and 16 lanes away) use the gfx950
+    // lane-swap instructions: swapping the upper half of v[q] with the lower
+    // half of v[q + h] leaves every lane holding its own element and its
+    // partner's, with no selects and no LDS traffic (FP64 addition is
+    // commutative, so the sums are the same as with the exchange below).
+    auto swap_add = [](double &x, double y, auto sw) {
+        const uint64_t ux = __builtin_bit_cast(uint64_t, x), uy = __builtin_bit_cast(uint64_t, y);
+        const auto lo = sw((uint32_t)ux, (uint32_t)uy);
+        const auto hi = sw((uint32_t)(ux >> 32), (uint32_t)(uy >> 32));
+        const double a = __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi[0] << 32) | (uint32_t)lo[0]);
+        const double b = __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi[1] << 32) | (uint32_t)lo[1]);
+        x = a + b;
+    };
+    auto sw32 = [](uint32_t a, uint32_t b) { return __builtin_amdgcn_permlane32_swap(a, b, false, false); };
+    auto sw16 = [](uint32_t a, uint32_t b) { return __builtin_amdgcn_permlane16_swap(a, b, false, false); };
 #pragma unroll
-    for (int h = 8, b = 32; h >= 1; h >>= 1, b >>= 1) {
+    for (int q = 0; q < 8; ++q) swap_add(v[q], v[q + 8], sw32);   // lanes >= 32 now hold outputs 8..15
+#pragma unroll
+    for (int q = 0; q < 4; ++q) swap_add(v[q], v[q + 4], sw16);   // odd rows of 16 hold outputs +4
+#pragma unroll
+    for (int h = 2, b = 8; h >= 1; h >>= 1, b >>= 1) {
         uint32_t up = (lane & b) ? ~0u : 0u;
         asm volatile("" : "+v"(up));
 #pragma unroll

@@ -238,13 +238,15 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     const int n = c * 16 + q;
                     const double Lf = f2[n * kFwdRow + 7] * (double)adj_exp2<T>(X[n]);
                     const double onep = 1.0 + delta * Lf;
+                    const double num_prev = num;
                     num *= onep;
                     const double rn = delta / num;
                     const double ex = Lf - f2[n * kFwdRow + 8];
                     const double flag = f2[n * kFwdRow + 9];
                     const double Pn = ex > 0.0 ? flag * (ex * rn) : 0.0;
                     if constexpr (GREEKS) {
-                        double dL = -delta / onep * (book - before);
+                        // delta / (1 + delta L_n) = rn num_{n-1}: no second division
+                        double dL = -(rn * num_prev) * (book - before);
                         if (ex > 0.0) dL += flag * rn;
                         vbar[n][lane] = (T)(dL * Lf * 0.69314718055994530942);
                         before += Pn;
