@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -407,6 +408,14 @@ rq_status check_lmm(const rq_lmm_model *m)
 // guards).
 int lmm_rows(int) { return rq::kMaxFwd; }
 
+// kappa_n = 1 / (delta L_n(0)) in T, the drift factor's constant; held finite
+// (a product with it then never forms 0 x inf)
+template <typename T>
+T inv_dl(double delta, double L0)
+{
+    return (T)std::min(1.0 / (delta * L0), (double)std::numeric_limits<T>::max());
+}
+
 // Forward tables: FP64 rows then FP32 rows (layout in rq_internal.h).
 std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
 {
@@ -433,8 +442,9 @@ std::vector<uint8_t> lmm_table(const rq_lmm_model *m)
         r[8] = std::isnan(K) ? 0.0 : K;
         r[9] = std::isnan(K) ? 0.0 : 1.0;
         r[10] = 1.0 / (m->L0[n] * 0.69314718055994530942);
+        r[11] = 1.0 / std::max(m->sigma[n], rq::kMinSigma);
         q[6] = (float)(log2e * r[6]);
-        q[7] = (float)std::log2(m->delta * m->L0[n]);
+        q[7] = inv_dl<float>(m->delta, m->L0[n]);
     }
     std::vector<uint8_t> out(t.size() * sizeof(double) + f32.size() * sizeof(float));
     std::memcpy(out.data(), t.data(), t.size() * sizeof(double));
@@ -454,22 +464,16 @@ std::vector<uint8_t> adj_table(const rq_lmm_model *m)
     std::vector<T> t((size_t)lmm_rows(nf) * rq::kAdjRow, T(0));
     for (int n = 1; n <= nf; ++n) {
         T *r = &t[(size_t)(n - 1) * rq::kAdjRow];
-        const double sg = m->sigma[n];
-        double b2 = 0.0, a2 = 0.0;
+        const double sg = std::max(m->sigma[n], rq::kMinSigma);
+        double a2 = 0.0;
         for (int f = 0; f < d; ++f) {
-            const double b = m->loadings[(size_t)(n - 1) * d + f];
-            const double a = sg * b;
+            const double a = sg * m->loadings[(size_t)(n - 1) * d + f];
             r[f] = (T)(log2e * a);
             r[3 + f] = (T)(m->delta * a);
-            r[9 + f] = (T)(log2e * b);
-            r[12 + f] = (T)(m->delta * b);
-            b2 += b * b;
             a2 += a * a;
         }
         r[6] = (T)(log2e * (-0.5 * a2 * m->delta));
-        r[7] = (T)std::log2(m->delta * m->L0[n]);
-        r[8] = (T)sg;
-        r[15] = (T)(log2e * m->delta * sg * b2);
+        r[7] = inv_dl<T>(m->delta, m->L0[n]);
     }
     std::vector<uint8_t> out(t.size() * sizeof(T));
     std::memcpy(out.data(), t.data(), out.size());

@@ -93,22 +93,27 @@ struct SetupArgs {
 //   [8]    K_n (0 when there is no caplet)
 //   [9]    1 if forward n carries a caplet, else 0
 //   [10]   1 / (L_n(0) ln 2)
+//   [11]   1 / sigma~_n, sigma~_n = max(sigma_n, 2^-60) (the adjoint's vega scale)
 // followed by the FP32 rows, kRow32 floats per forward, log2 units:
 //   [0..2] log2(e) a_n
 //   [3..5] delta a_n
 //   [6]    log2(e) c_n
-//   [7]    log2(delta L_n(0))
+//   [7]    kappa_n = 1 / (delta L_n(0))  (the drift factor is 1 / (1 + kappa_n 2^{-X_n}))
 // Every table has kMaxFwd rows; the rows beyond n_fwd are zero.
 constexpr int kFwdRow = 12;
 constexpr int kRow32 = 8;
 constexpr int kGrp = 4;   // forwards per branch-free group of the LIBOR kernel
 
-// Adjoint table, kAdjRow entries per forward in the kernel's precision:
-//   [0..2] log2(e) a_n     [3..5] delta a_n     [6] log2(e) c_n
-//   [7]    log2(delta L_n(0))                    [8] sigma_n
-//   [9..11] log2(e) b_n    [12..14] delta b_n   [15] log2(e) delta sigma_n |b_n|^2
-// where b_n = a_n / sigma_n is the unit loading row.
-constexpr int kAdjRow = 16;
+// Adjoint table, kAdjRow entries per forward in the kernel's precision, the
+// FP32 row's layout with a_n = sigma~_n b_n (b_n the unit loading row):
+//   [0..2] log2(e) a_n     [3..5] delta a_n
+//   [6]    log2(e) c_n = -log2(e) delta |a_n|^2 / 2
+//   [7]    1 / (delta L_n(0))
+// A zero sigma_n enters as sigma~_n = 2^-60: the increments it adds to the
+// state and to w lie far below their rounding, and the vega it gives is the
+// derivative at 2^-60, equal to the one at 0 up to O(2^-60).
+constexpr int kAdjRow = 8;
+constexpr double kMinSigma = 0x1p-60;
 
 struct LmmArgs {
     SeqGeom g;

@@ -15,9 +15,9 @@
 // the time loop from the final state.
 //
 // FP32 form: the lane keeps X_n = log2(L_n / L_n(0)).  With the constant
-// l_n = log2(delta L_n(0)) the drift factor is
-//   g_n = 1 / (1 + 2^{-(X_n + l_n)})
-// (one add, one v_exp_f32, one add, one v_rcp_f32), and the step is
+// kappa_n = 1 / (delta L_n(0)) the drift factor is
+//   g_n = delta L_n / (1 + delta L_n) = 1 / (1 + kappa_n 2^{-X_n})
+// (one v_exp_f32, one fused multiply-add, one v_rcp_f32), and the step is
 //   X_n += log2(e) (a_n . w + c_n),
 // the (small) increment being formed before it is added, so the O(1) state
 // rounds once per step at its own scale (~3e-8) and the exponential's error
@@ -98,8 +98,7 @@ void lmm_kernel(LmmArgs a)
         auto body = [&](int n) __attribute__((always_inline)) {
             if constexpr (kF32) {
                 const float *q = a.fwd32 + n * kRow32;
-                const float s = X[n] + q[7];            // log2(delta L_n)
-                const float g = __builtin_amdgcn_rcpf(1.0f + fexp2(-s));
+                const float g = __builtin_amdgcn_rcpf(ffma(q[7], fexp2(-X[n]), 1.0f));
 #pragma unroll
                 for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
                 // form the (small) step increment first, then add it to the

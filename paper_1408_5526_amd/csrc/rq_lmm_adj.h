@@ -3,7 +3,7 @@
 //
 // Forward pass (same scheme as rq_lmm.hip, state X_n = log2(L_n / L_n(0))):
 //   step k:  w = sqrt(delta) z_k;  for n = k..n_fwd-1 in ascending order:
-//     g_n = G(X_n) = 1 / (1 + 2^{-(X_n + l_n)}),  l_n = log2(delta L_n(0))
+//     g_n = G(X_n) = 1 / (1 + kappa_n 2^{-X_n}),  kappa_n = 1 / (delta L_n(0))
 //     w  += g_n delta a_n                       (w is now w_n)
 //     X_n += log2(e) (c_n + a_n . w_n)
 //   and the lane stores the step's final w (d numbers).
@@ -16,12 +16,18 @@
 // k = n_fwd-1..0.  Step k restarts from its stored final w and visits its
 // forwards in descending order.  With w_n known, the pre-step state and the
 // drift factor are explicit (nothing is solved, no normal is drawn again):
-//   X_n -= log2(e) (c_n + a_n . w_n),   g_n = G(X_n)
+//   P = log2(e) a_n . w_n,   X_n -= P + log2(e) c_n,   g_n = G(X_n)
 // and the adjoint of the forward-step is
 //   Wbar += Xbar_n log2(e) a_n            (adjoint of w_n: a suffix sum over n)
-//   vega_n += Xbar_n log2(e) (b_n . w_n - delta sigma_n |b_n|^2) + g_n delta b_n . Wbar
-//   Xbar_n += (delta a_n . Wbar) G'(X_n),  G' = ln2 G (1 - G)
+//   h     = g_n delta a_n . Wbar
+//   vega_n += Xbar_n log2(e) (b_n . w_n - delta sigma_n |b_n|^2) + h / sigma_n
+//   Xbar_n += h ln2 (1 - g_n)             (delta a_n . Wbar G'(X_n), G' = ln2 G (1 - G))
 //   w    -= g_n delta a_n                 (back to w_{n-1})
+// with a_n = sigma_n b_n.  The lane accumulates sigma_n vega_n,
+//   sigma_n vega_n += Xbar_n (P - 2 log2(e) c_n) + h,
+// so that the one dot product P serves the state and the vega, and h both
+// the vega and Xbar with constant factors; the sums are divided by sigma_n
+// once, in FP64, at the end (a zero sigma_n is carried as 2^-60).
 // After step 0, Xbar_n is the adjoint of log2 L_n(0), so
 //   dbook/dL_n(0) = Xbar_n / (L_n(0) ln 2);  dbook/dL_0(0) = -delta book / num_0.
 // The reconstructed states differ from the forward pass's by rounding only
@@ -105,7 +111,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     const double delta = a.delta;
     const T sqd = (T)a.sqrt_delta;
 
-    auto G = [&](T s) -> T { return adj_rcp<T>(T(1) + adj_exp2<T>(-s)); };
+    auto G = [&](T x, T c) -> T { return adj_rcp<T>(ffma(c, adj_exp2<T>(-x), T(1))); };
 
     const int64_t i = (int64_t)blk * kWave + lane;
     const bool active = i < a.g.N;
@@ -139,7 +145,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         // one forward-step of forward n (alive in this step)
         auto body = [&](int n) __attribute__((always_inline)) {
             const cptr<T> q = tab + n * kAdjRow;
-            const T g = G(X[n] + q[7]);
+            const T g = G(X[n], q[7]);
 #pragma unroll
             for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
             // the (small) increment log2(e) (c_n + a_n . w) is formed first and
@@ -295,11 +301,8 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             for (int f = 0; f < D; ++f) wn[f] = wt[(size_t)((k - 1) * D + f) * kWave];
         }
         // adjoint of one forward-step, w = w_n on entry, w_{n-1} on exit;
-        // on = 0 leaves everything unchanged
-        // (a_n = sigma_n b_n, so a_n . w = sigma_n b_n . w and
-        // delta a_n . Wbar = sigma_n delta b_n . Wbar: two dot products serve
-        // the state, the vega and the drift-factor adjoint).  q is the
-        // forward's table row and vb its vega entry so far.  pre() runs right
+        // on = 0 leaves everything unchanged.  q is the forward's table row
+        // and vb its (sigma-scaled) vega entry so far.  pre() runs right
         // after the row's first use, once the wave has waited for the row: it
         // issues the next forward's row and vega loads and stores the previous
         // forward-step's vega entry, so that the one wait per forward-step
@@ -308,31 +311,31 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         const int nfk = opaque_u(nf);   // tests on it stay inside the step loop
         auto body = [&](int n, const auto &q, T vb, T on, auto masked, auto pre) __attribute__((always_inline)) {
             constexpr bool MASKED = decltype(masked)::value;
-            T bw = q[9] * w[0];                       // log2(e) b_n . w_n
+            T P = q[0] * w[0];                        // log2(e) a_n . w_n
 #pragma unroll
-            for (int f = 1; f < D; ++f) bw = ffma(q[9 + f], w[f], bw);
+            for (int f = 1; f < D; ++f) P = ffma(q[f], w[f], P);
             if constexpr (!std::is_same<decltype(pre), NoPre>::value) {
                 __builtin_amdgcn_sched_barrier(0);
                 pre();
                 __builtin_amdgcn_sched_barrier(0);
             }
-            const T y = MASKED ? ffma(-ffma(q[8], bw, q[6]), on, X[n]) : ffma(-q[8], bw, X[n] - q[6]);
+            const T y = MASKED ? ffma(-(P + q[6]), on, X[n]) : X[n] - (P + q[6]);
             X[n] = y;
-            const T g = G(y + q[7]);
+            const T g = G(y, q[7]);
             const T ge = MASKED ? g * on : g;
             const T xb = MASKED ? Xb[n] * on : Xb[n];
 #pragma unroll
             for (int f = 0; f < D; ++f) Wb[f] = ffma(xb, q[f], Wb[f]);
-            T dbw = q[12] * Wb[0];                    // delta b_n . Wbar
+            T da = q[3] * Wb[0];                      // delta a_n . Wbar
 #pragma unroll
-            for (int f = 1; f < D; ++f) dbw = ffma(q[12 + f], Wb[f], dbw);
-            const T h = ge * dbw;
-            const T vnew = vb + ffma(xb, bw - q[15], h);
+            for (int f = 1; f < D; ++f) da = ffma(q[3 + f], Wb[f], da);
+            const T h = ge * da;
+            const T vnew = vb + ffma(xb, ffma(T(2), q[6], P), h);
             if constexpr (MASKED || std::is_same<decltype(pre), NoPre>::value)
                 vbar[n][lane] = vnew;
             else
                 pend = vnew;   // written by the next forward-step, after its wait
-            Xb[n] = ffma(q[8] * h, ffma(-kLn2, g, kLn2), Xb[n]);
+            Xb[n] = ffma(kLn2, ffma(-g, h, h), Xb[n]);
 #pragma unroll
             for (int f = 0; f < D; ++f) w[f] = ffma(-ge, q[3 + f], w[f]);
         };
@@ -361,7 +364,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                         for (int e = 0; e < kAdjRow; ++e) q[e] = rr[e];
                         const T vb = vo;
                         body(n, q, vb, T(1), std::false_type{}, [&] {
-                            const cptr<T> t2 = after(tab, q[9]);
+                            const cptr<T> t2 = after(tab, q[0]);
                             __builtin_amdgcn_sched_barrier(0);
                             if (n > 0) {
                                 load_row(rr, t2 + (n - 1) * kAdjRow);
@@ -399,8 +402,9 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     }
 
     // ---- Greeks [2 nf + 1]: deltas, spot delta (above), vegas ----
-    // dbook/dL_n(0) = Xbar_n / (L_n(0) ln 2): row entry 10 is 1/(L_n(0) ln 2),
-    // 0 beyond n_fwd, where Xbar and the vega rows are 0 as well
+    // dbook/dL_n(0) = Xbar_n / (L_n(0) ln 2): row entry 10 is 1/(L_n(0) ln 2)
+    // and entry 11 the vega rows' 1/sigma~_n, both 0 beyond n_fwd, where Xbar
+    // and the vega rows are 0 as well
     const cptr<double> f3 = opaque_u(fwd);
 #pragma unroll
     for (int c = 0; c < NFC / 16; ++c) {
@@ -416,7 +420,8 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             double s = wave_sum16(V, lane);
             if (wr) gout[o] = s;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) V[q] = (double)vbar[c * 16 + q][lane] * act;
+            for (int q = 0; q < 16; ++q)   // sigma_n vega_n / sigma_n
+                V[q] = (double)vbar[c * 16 + q][lane] * f3[(c * 16 + q) * kFwdRow + 11] * act;
             s = wave_sum16(V, lane);
             if (wr) gout[nf + 1 + o] = s;
         }
