@@ -184,7 +184,10 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
  *             n_g = 2 n_fwd + 1 outputs per replication: [0, n_fwd)
  *             dbook/dL_n(0) for n = 1..n_fwd (strikes held fixed); [n_fwd]
  *             dbook/dL_0(0) (the spot rate, through the numeraire);
- *             [n_fwd + 1, 2 n_fwd + 1) dbook/dsigma_n for n = 1..n_fwd.
+ *             [n_fwd + 1, 2 n_fwd + 1) dbook/dsigma_n for n = 1..n_fwd
+ *             (the adjoint carries a sigma_n below 2^-60, zero included,
+ *             as 2^-60: its state and prices are unchanged to rounding and
+ *             its vega is the derivative there).
  *             theta holds the per-replication estimates, mean/sd/se their
  *             grand average and spread (as for prices).
  *   per_path  optional device [M][N][n_out] FP64: every path's discounted
