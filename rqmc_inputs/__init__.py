@@ -157,6 +157,23 @@ def mbs_paper(months: int = 360, sigma: float = 0.02) -> MbsParams:
                      K1=0.01, K2=-0.005, K3=10.0, K4=0.5)
 
 
+def lmm_stress(n_fwd: int = 12, n_factors: int = 2) -> LmmModel:
+    """An extreme-regime model for robustness tests: semi-annual forwards
+    from 1e-4 up to 15% (log-spaced), volatilities up to 120% with two zero
+    volatilities, ATM caplets except on two forwards."""
+    delta = 0.5
+    T = np.arange(n_fwd + 1, dtype=np.float64) * delta
+    L0 = 10.0 ** np.linspace(-4.0, math.log10(0.15), n_fwd + 1)
+    sigma = 0.3 + 0.9 * np.abs(np.sin(1.7 * np.arange(n_fwd + 1)))
+    sigma[0] = 0.0
+    sigma[[3, 8]] = 0.0
+    B = pca_loadings(T[1:], 0.3, n_factors)
+    strike = L0[1:].copy()
+    strike[[1, 6]] = np.nan
+    return LmmModel(n_fwd=n_fwd, n_factors=n_factors, delta=delta, L0=L0, sigma=sigma,
+                    loadings=B, strike=strike)
+
+
 def small_lmm(n_fwd: int = 6, n_factors: int = 2, delta: float = 0.25) -> LmmModel:
     """A small multi-factor model on the 80-forward curve family, for tests."""
     return lmm_curve80(n_fwd=n_fwd, n_factors=n_factors, delta=delta)

@@ -153,6 +153,7 @@ LMM = [
     ("nf20d3-mc", lambda: I.lmm_curve80(20, 3), 513, 2, 5, rq.MC_PHILOX),
     ("nf80d3-mc", lambda: I.lmm_curve80(), 300, 2, 3, rq.MC_PHILOX),
     ("nf20d3-permrep", lambda: I.lmm_curve80(20, 3), 513, 3, 5, rq.PERM_PER_REP),
+    ("stress", I.lmm_stress, 700, 2, 21, 0),      # rates 1e-4..15%, vols to 120% and 0
 ]
 
 
@@ -188,6 +189,7 @@ LMM32 = [
     ("nf33d1-perm", lambda: I.lmm_curve80(33, 1), 4097, 2, 9, rq.PERM_RANDOM),
     ("nf20d3-mc", lambda: I.lmm_curve80(20, 3), 4200, 2, 5, rq.MC_PHILOX),
     ("nf33d1-permrep", lambda: I.lmm_curve80(33, 1), 4097, 3, 9, rq.PERM_PER_REP),
+    ("stress", I.lmm_stress, 4133, 2, 21, 0),
 ]
 
 
