@@ -215,8 +215,11 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     // through a fresh pointer so that no row value stays live in scalar
     // registers from one pass to the next.
     if constexpr (GREEKS) {
+        // the book over a common denominator: B = num_{n+1} sum_{j<=n} P_j
+        // grows as B <- B (1 + delta L_n) + delta (L_n - K_n)^+, and
+        // book = B / num at the end (one division instead of one per forward)
         const cptr<double> f1 = opaque_u(fwd);
-        double num = a.num0;
+        double num = a.num0, B = 0.0;
 #pragma unroll
         for (int c = 0; c < NFC / 16; ++c) {
             if (c * 16 < nf) {
@@ -224,12 +227,14 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                 for (int q = 0; q < 16; ++q) {
                     const int n = c * 16 + q;
                     const double Lf = f1[n * kFwdRow + 7] * (double)adj_exp2<T>(X[n]);
-                    num *= 1.0 + delta * Lf;
+                    const double onep = 1.0 + delta * Lf;
+                    num *= onep;
                     const double ex = Lf - f1[n * kFwdRow + 8];
-                    book += ex > 0.0 ? f1[n * kFwdRow + 9] * (delta * ex / num) : 0.0;
+                    B = __builtin_fma(B, onep, ex > 0.0 ? f1[n * kFwdRow + 9] * (delta * ex) : 0.0);
                 }
             }
         }
+        book = B / num;
     }
     {
         const cptr<double> f2 = opaque_u(fwd);
