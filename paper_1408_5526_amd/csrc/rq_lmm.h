@@ -187,8 +187,8 @@ void lmm_kernel(LmmArgs a)
                 const double Lf = kF32 ? r64(n, 7) * (double)fexp2((float)X[n]) : (double)X[n];
                 const double onep = 1.0 + delta * Lf;
                 const double ex = Lf - r64(n, 8);
-                double pay = ex > 0.0 ? r64(n, 9) * (delta * ex / (num * onep)) : 0.0;
                 num *= onep;
+                double pay = ex > 0.0 ? r64(n, 9) * (delta * ex * recip64(num)) : 0.0;
                 pay = active ? pay : 0.0;
                 book += pay;
                 if (pp) pp[n < nf ? n : nf] = pay;   // beyond n_fwd: 0 into the book slot, rewritten below

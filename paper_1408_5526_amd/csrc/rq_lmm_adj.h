@@ -251,7 +251,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     const double onep = 1.0 + delta * Lf;
                     const double num_prev = num;
                     num *= onep;
-                    const double rn = delta / num;
+                    const double rn = delta * recip64(num);
                     const double ex = Lf - f2[n * kFwdRow + 8];
                     const double flag = f2[n * kFwdRow + 9];
                     const double Pn = ex > 0.0 ? flag * (ex * rn) : 0.0;
