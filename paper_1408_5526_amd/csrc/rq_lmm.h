@@ -81,6 +81,17 @@ void lmm_kernel(LmmArgs a)
 #pragma unroll 1
     for (int k = 0; k < nf; ++k) {
         T w[D];
+        // the step's base and start entries, all requested before the first
+        // is used: one scalar-load wait per step instead of one per dimension
+        PointCtx cs[D];
+        StartEnt ses[D];
+        if constexpr (GEN != 2) {
+#pragma unroll
+            for (int f = 0; f < D; ++f) {
+                cs[f] = load_base_uniform(a.g.base, k * D + f);
+                ses[f] = load_uniform<StartEnt>(st + k * D + f);
+            }
+        }
 #pragma unroll
         for (int f = 0; f < D; ++f) {
             const int j = k * D + f;
@@ -88,9 +99,7 @@ void lmm_kernel(LmmArgs a)
             if constexpr (GEN == 2) {
                 x = mc.point(a.g.seed, (uint64_t)(a.g.m_offset + m), (uint64_t)i, j);
             } else {
-                const PointCtx c = load_base_uniform(a.g.base, j);
-                x = radinv_x<GEN == 1, sizeof(T) == 8>(c, load_uniform<StartEnt>(st + j), t,
-                                                       a.g.perm + (size_t)m * a.g.perm_stride);
+                x = radinv_x<GEN == 1, sizeof(T) == 8>(cs[f], ses[f], t, a.g.perm + (size_t)m * a.g.perm_stride);
             }
             w[f] = sqd * inv_normal(x, T(0));
         }

@@ -128,6 +128,17 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll 1
     for (int k = 0; k < (PART == kTaskRev ? 0 : nf); ++k) {
         T w[D];
+        // the step's base and start entries, all requested before the first
+        // is used: one scalar-load wait per step instead of one per dimension
+        PointCtx cs[D];
+        StartEnt ses[D];
+        if constexpr (!MC) {
+#pragma unroll
+            for (int f = 0; f < D; ++f) {
+                cs[f] = load_base_uniform(a.g.base, k * D + f);
+                ses[f] = load_uniform<StartEnt>(st + k * D + f);
+            }
+        }
 #pragma unroll
         for (int f = 0; f < D; ++f) {
             const int j = k * D + f;
@@ -135,10 +146,8 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             if constexpr (MC) {
                 x = mc.point(a.g.seed, (uint64_t)(a.g.m_offset + m), (uint64_t)i, j);
             } else {
-                const PointCtx c = load_base_uniform(a.g.base, j);
-                const StartEnt se = load_uniform<StartEnt>(st + j);
-                x = a.g.perm_on ? radinv_x<true, !kF32>(c, se, t, a.g.perm + (size_t)m * a.g.perm_stride)
-                                : radinv_x<false, !kF32>(c, se, t, a.g.perm);
+                x = a.g.perm_on ? radinv_x<true, !kF32>(cs[f], ses[f], t, a.g.perm + (size_t)m * a.g.perm_stride)
+                                : radinv_x<false, !kF32>(cs[f], ses[f], t, a.g.perm);
             }
             w[f] = sqd * inv_normal(x, T(0));
         }
