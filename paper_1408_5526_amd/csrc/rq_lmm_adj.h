@@ -399,9 +399,14 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             for (int gq = NFC / kGrp - 1; gq >= 0; --gq) {
                 const int n0 = gq * kGrp;
                 if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {        // n0 < k < n0 + kGrp
+                    // the group's rows, all requested before the first is used
+                    // (one scalar-load wait for the group, not one per forward)
+                    T qg[kGrp][kAdjRow];
+#pragma unroll
+                    for (int u = 0; u < kGrp; ++u) load_row(qg[u], tab + (n0 + u) * kAdjRow);
 #pragma unroll
                     for (int u = kGrp - 1; u >= 0; --u)   // masked (branches here cost SGPRs the loop needs)
-                        body(n0 + u, tab + (n0 + u) * kAdjRow, vbar[n0 + u][lane],
+                        body(n0 + u, qg[u], vbar[n0 + u][lane],
                              __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                                  (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
                              std::true_type{}, none);
