@@ -191,11 +191,11 @@ class Result:
 
 
 def _result(M: int, n_out: int, device):
+    # one allocation, four views: theta [M][n_out], then mean, sd, se
     torch = _torch()
-    theta = torch.empty((M, n_out), dtype=torch.float64, device=device)
-    mean = torch.empty(n_out, dtype=torch.float64, device=device)
-    sd = torch.empty(n_out, dtype=torch.float64, device=device)
-    se = torch.empty(n_out, dtype=torch.float64, device=device)
+    buf = torch.empty((M + 3) * n_out, dtype=torch.float64, device=device)
+    theta = buf[:M * n_out].view(M, n_out)
+    mean, sd, se = (buf[(M + r) * n_out:(M + r + 1) * n_out] for r in range(3))
     c = rq_result(theta.data_ptr(), mean.data_ptr(), sd.data_ptr(), se.data_ptr())
     return Result(theta, mean, sd, se), c
 
