@@ -19,6 +19,8 @@ import math
 import numpy as np
 from scipy.stats import norm
 
+import oracle as O
+
 
 def black_caplets(model):
     """C_n for n = 1..n_fwd (0 where the strike is NaN)."""
@@ -58,3 +60,38 @@ def black_book_greeks(model):
         out[n - 1] = d * B * norm.cdf(d1) + disc
         out[nf + n] = d * B * L * norm.pdf(d1) * math.sqrt(T)
     return out
+
+
+def crn_bias_greeks(model, n_paths, seed, h_rel=1e-5):
+    """Richardson estimate of the scheme's bias in each book Greek:
+    b = 2 (G_delta - G_delta/2), G by central differences of the oracle's
+    paths on shared pseudo-random normals (the coarse normal of a period is
+    (z_a + z_b)/sqrt 2 of its two halves).  Returns (b, SE of b)."""
+    rng = np.random.default_rng(seed)
+    nf, d = model.n_fwd, model.n_factors
+    zf = rng.standard_normal((n_paths, nf, 2, d))
+    zc = ((zf[:, :, 0, :] + zf[:, :, 1, :]) / math.sqrt(2.0)).reshape(n_paths, -1)
+    zf = zf.reshape(n_paths, -1)
+
+    def diff(mm):
+        return 2.0 * (O.lmm_paths(mm, zc, n_sub=1)[:, -1] - O.lmm_paths(mm, zf, n_sub=2)[:, -1])
+
+    mean, se = np.zeros(2 * nf + 1), np.zeros(2 * nf + 1)
+
+    def put(col, up, dn, h):
+        v = (diff(up) - diff(dn)) / (2 * h)
+        mean[col], se[col] = v.mean(), v.std(ddof=1) / math.sqrt(n_paths)
+
+    for n in range(nf + 1):
+        h = h_rel * model.L0[n]
+        up, dn = model.copy(), model.copy()
+        up.L0[n] += h
+        dn.L0[n] -= h
+        put(nf if n == 0 else n - 1, up, dn, h)
+    for n in range(1, nf + 1):
+        h = h_rel * max(model.sigma[n], 0.01)
+        up, dn = model.copy(), model.copy()
+        up.sigma[n] += h
+        dn.sigma[n] -= h
+        put(nf + n, up, dn, h)
+    return mean, se

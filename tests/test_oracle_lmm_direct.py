@@ -26,7 +26,7 @@ import pytest
 
 import oracle as O
 import rqmc_inputs as I
-from black_caplet import black_book_greeks, black_caplets
+from black_caplet import black_book_greeks, black_caplets, crn_bias_greeks
 
 mp.mp.dps = 40
 
@@ -161,3 +161,38 @@ def test_black_greek_formulas_are_derivatives_of_black_price(mk):
         dn.sigma[n] -= h
         fd[nf + n] = (black_caplets(up).sum() - black_caplets(dn).sum()) / (2 * h)
     assert np.allclose(g, fd, rtol=1e-7, atol=1e-9 * np.abs(fd).max())
+
+
+def _fd_book_greeks(model, N, M, seed, h_rel):
+    """theta-level central differences of the oracle's book (same points),
+    layout [dL_1..dL_n, dL_0, dsigma_1..dsigma_n] per replication."""
+    nf = model.n_fwd
+    out = np.zeros((M, 2 * nf + 1))
+    for n in range(nf + 1):
+        h = h_rel * model.L0[n]
+        up, dn = model.copy(), model.copy()
+        up.L0[n] += h
+        dn.L0[n] -= h
+        out[:, nf if n == 0 else n - 1] = (O.price_caplets(up, N, M, seed)[:, -1] -
+                                           O.price_caplets(dn, N, M, seed)[:, -1]) / (2 * h)
+    for n in range(1, nf + 1):
+        h = h_rel * model.sigma[n]
+        up, dn = model.copy(), model.copy()
+        up.sigma[n] += h
+        dn.sigma[n] -= h
+        out[:, nf + n] = (O.price_caplets(up, N, M, seed)[:, -1] -
+                          O.price_caplets(dn, N, M, seed)[:, -1]) / (2 * h)
+    return out
+
+
+@pytest.mark.parametrize("mk,N,M,seed", [(lambda: I.cfg1().model, 4096, 32, 1),
+                                         (lambda: I.small_lmm(6, 2), 1 << 13, 32, 17)],
+                         ids=["cfg1", "nf6d2"])
+def test_oracle_fd_greeks_match_black_within_se_plus_bias(mk, N, M, seed):
+    # the finite-difference Greeks the GPU adjoint is compared with, checked
+    # against Black's Greeks plus the scheme's Richardson bias estimate
+    m = mk()
+    rqv, sd, se = O.finalize(_fd_book_greeks(m, N, M, seed, 1e-6))
+    b, se_b = crn_bias_greeks(m, 100_000, seed=3)
+    z = (rqv - black_book_greeks(m) - b) / np.sqrt(se ** 2 + se_b ** 2)
+    assert (np.abs(z) <= 3.0).all(), z
