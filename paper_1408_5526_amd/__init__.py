@@ -554,3 +554,67 @@ def timer_part(part: int):
 
 def version() -> str:
     return lib().rq_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# the CPU baseline generator (librqmc_cpu.so, include/rqmc_cpu.h): the
+# paper's recursive Halton method (Algorithm 2) on the host's cores, the
+# comparison for rq_sequence; no GPU entry point uses it
+# ---------------------------------------------------------------------------
+CPU_LIB_PATH = os.path.join(HERE, "librqmc_cpu.so")
+_cpu_lib = None
+
+
+def cpu_lib():
+    """The loaded CPU generator library (raises if it has not been built)."""
+    global _cpu_lib
+    if _cpu_lib is not None:
+        return _cpu_lib
+    if not os.path.exists(CPU_LIB_PATH):
+        raise RuntimeError(f"CPU generator library {CPU_LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    L = C.CDLL(CPU_LIB_PATH)
+    L.rq_cpu_last_error.restype = C.c_char_p
+    L.rq_cpu_last_error.argtypes = []
+    L.rq_cpu_max_threads.restype = C.c_int
+    L.rq_cpu_max_threads.argtypes = []
+    L.rq_cpu_sequence.restype = C.c_int
+    L.rq_cpu_sequence.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_uint64, C.c_int, C.c_int64, C.c_void_p,
+                                  C.c_int]
+    L.rq_cpu_alg2_run.restype = C.c_int
+    L.rq_cpu_alg2_run.argtypes = [C.c_uint32, C.c_void_p, C.c_uint64, C.c_int64, C.c_void_p]
+    _cpu_lib = L
+    return L
+
+
+def _cpu_check(st: int):
+    if st != RQ_OK:
+        raise RqError(st, cpu_lib().rq_cpu_last_error().decode())
+
+
+def cpu_max_threads() -> int:
+    return int(cpu_lib().rq_cpu_max_threads())
+
+
+def cpu_sequence(s: int, N: int, M: int, seed: int, flags: int = 0, m_offset: int = 0,
+                 threads: int = 0, out=None) -> np.ndarray:
+    """The points of sequence() computed on the host by the recursive
+    generator: numpy [M][N][s] FP64, bit-identical to the GPU's."""
+    if out is None:
+        out = np.empty((M, N, s), dtype=np.float64)
+    if out.dtype != np.float64 or not out.flags.c_contiguous or out.size < M * N * s:
+        raise ValueError("out must be a C-contiguous float64 array of M*N*s elements")
+    _cpu_check(cpu_lib().rq_cpu_sequence(s, N, M, seed, flags, m_offset, out.ctypes.data, threads))
+    return out
+
+
+def cpu_alg2_run(p: int, n: int, count: int, sigma=None) -> np.ndarray:
+    """The exact integers R of `count` consecutive indices from n in base p
+    (uint64), by the recursive generator."""
+    out = np.empty(count, dtype=np.uint64)
+    sg = None
+    if sigma is not None:
+        sg = np.ascontiguousarray(sigma, dtype=np.int32)
+    _cpu_check(cpu_lib().rq_cpu_alg2_run(p, sg.ctypes.data if sg is not None else None, n, count,
+                                         out.ctypes.data))
+    return out

@@ -68,6 +68,26 @@ def build(verbose: bool = False, only_if_stale: bool = False, jobs: int = 8) -> 
     return LIB
 
 
+# The CPU baseline generator (Algorithm 2, multi-core and SIMD): a host-only
+# library of its own, built with g++ for x86-64-v3 (AVX2, FMA).
+CSRC_CPU = os.path.join(HERE, "csrc_cpu")
+LIB_CPU = os.path.join(HERE, "librqmc_cpu.so")
+
+
+def build_cpu(verbose: bool = False) -> str:
+    src = os.path.join(CSRC_CPU, "rq_cpu_alg2.cpp")
+    cmd = ["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-march=x86-64-v3",
+           "-ffp-contract=off", "-Wall", "-Wextra", "-I" + INCLUDE, src, "-o", LIB_CPU + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"g++ failed on rq_cpu_alg2.cpp:\n{r.stdout}\n{r.stderr}")
+    os.replace(LIB_CPU + ".tmp", LIB_CPU)
+    return LIB_CPU
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
-    print(LIB)
+    build_cpu(verbose="-v" in sys.argv)
+    print(LIB, LIB_CPU)
