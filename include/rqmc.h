@@ -293,14 +293,30 @@ rq_status rq_price_batch(const rq_instrument *inst, int n_inst, rq_precision pre
                          const rq_tuning *tuning, const rq_result *outs, const rq_result *grads,
                          uint64_t *t_first, uint64_t *t_last, void *ws, size_t ws_bytes, void *stream);
 
-/* autotune_batch: times price_batch on this batch for a fixed set of launch
- * shapes (chunk in {1, 2, 4, 8}; the resident and half the resident blocks
- * per CU; both orders), one untimed run first, and returns the fastest in
- * *best (and its time in ms in *best_ms unless NULL).  The outputs hold the
- * last run's results.  Synchronises the stream. */
+/* autotune_batch: the project's launch-shape autotuner for price_batch.
+ * Candidates: chunk (work items per queue grab) in {1, 2, 4, 8, 16} x
+ * waves_per_cu in {the resident count, half of it} x both orders (20
+ * shapes).  After one untimed run it times every candidate once; a batch of
+ * more than 2^28 paths is screened on a probe of itself (each instrument's
+ * M divided by the power of two that brings the probe near 2^28 paths, at
+ * least 1) and the three fastest shapes there are timed on the full batch
+ * (after one untimed full run).  The fastest shape is returned in *best
+ * (its full-batch time in ms in *best_ms unless NULL) and kept for this
+ * batch's signature (precision, Greeks, and per instrument its kind,
+ * shape, N, M and flags): rq_price_batch with tuning == NULL then uses it.
+ * With the environment variable RQ_TUNING_CACHE naming a file, the choice
+ * is also appended there and read back by later processes.  The outputs
+ * hold the last run's results.  Synchronises the stream. */
 rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks,
                             const rq_result *outs, const rq_result *grads, rq_tuning *best, double *best_ms,
                             void *ws, size_t ws_bytes, void *stream);
+
+/* batch_tuning: the launch shape rq_price_batch uses for this batch when
+ * called with tuning == NULL: the autotuner's choice for its signature
+ * (*from_autotuner = 1), else all zero, i.e. automatic (*from_autotuner =
+ * 0).  Host only; validates the list like rq_batch_workspace. */
+rq_status rq_batch_tuning(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks,
+                          rq_tuning *out, int *from_autotuner);
 
 /* Frequency (Hz) of the device real-time counter of the batch timestamps. */
 rq_status rq_realtime_hz(double *hz);

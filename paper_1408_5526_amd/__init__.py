@@ -112,6 +112,9 @@ def lib():
     L.rq_autotune_batch.argtypes = [C.POINTER(rq_instrument), C.c_int, C.c_int, C.c_int,
                                     C.POINTER(rq_result), C.POINTER(rq_result), C.POINTER(rq_tuning),
                                     C.POINTER(C.c_double), C.c_void_p, C.c_size_t, C.c_void_p]
+    L.rq_batch_tuning.restype = C.c_int
+    L.rq_batch_tuning.argtypes = [C.POINTER(rq_instrument), C.c_int, C.c_int, C.c_int, C.POINTER(rq_tuning),
+                                  C.POINTER(C.c_int)]
     L.rq_realtime_hz.restype = C.c_int
     L.rq_realtime_hz.argtypes = [C.POINTER(C.c_double)]
     L.rq_lmm_pca_loadings.restype = C.c_int
@@ -406,7 +409,9 @@ def price_batch(instruments, precision="fp32", greeks: bool = False, tuning=None
 
 def autotune_batch(instruments, precision="fp32", greeks: bool = False, device=None, ws=None):
     """(chunk, waves_per_cu, order) of the fastest launch shape for this
-    batch, and its time in ms (times every candidate shape once)."""
+    batch, and its time in ms (rq_autotune_batch: 20 candidate shapes, a
+    large batch screened on a probe of itself).  price_batch with
+    tuning=None then uses the choice for this list."""
     dev = _device(device)
     h = _BatchHost(instruments)
     prec = _prec(precision)
@@ -422,6 +427,17 @@ def autotune_batch(instruments, precision="fp32", greeks: bool = False, device=N
                                    C.byref(best), C.byref(ms), C.c_void_p(ws.data_ptr()), ws.numel(),
                                    _stream(dev)))
     return (best.chunk, best.waves_per_cu, best.order), ms.value
+
+
+def batch_tuning(instruments, precision="fp32", greeks: bool = False):
+    """((chunk, waves_per_cu, order), from_autotuner): the launch shape
+    price_batch uses for this list with tuning=None -- the autotuner's
+    choice for the list's signature, else all zero (automatic)."""
+    h = _BatchHost(instruments)
+    t = rq_tuning()
+    hit = C.c_int(0)
+    _check(lib().rq_batch_tuning(h.arr, h.n, _prec(precision), int(greeks), C.byref(t), C.byref(hit)))
+    return (t.chunk, t.waves_per_cu, t.order), bool(hit.value)
 
 
 def realtime_hz() -> float:

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <mutex>
@@ -715,11 +716,101 @@ int device_cus()
     return n;
 }
 
+// ---- the autotuner's choices, kept per batch signature ---------------------
+// The signature covers what decides the time of a batch: the precision, the
+// Greeks, and per instrument its kind, shape (forwards and factors, or
+// months), N, M and flags (FNV-1a over those fields).  rq_autotune_batch
+// stores its choice here, and rq_price_batch without a tuning uses it.  With
+// RQ_TUNING_CACHE naming a file, choices are appended to it and the file's
+// lines ("signature chunk waves_per_cu order", hexadecimal signature) are
+// read on first use, so that they outlive the process.
+uint64_t batch_signature(const rq_instrument *inst, int n_inst, rq_precision prec, bool greeks)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)(v >> (8 * b)) & 0xffu;
+            h *= 0x100000001b3ull;
+        }
+    };
+    mix(prec);
+    mix(greeks ? 1 : 0);
+    mix(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        const rq_instrument &I = inst[k];
+        mix(I.kind);
+        mix(I.N);
+        mix(I.M);
+        mix(I.flags);
+        if (I.kind == RQ_INST_LMM && I.lmm) {
+            mix(I.lmm->n_fwd);
+            mix(I.lmm->n_factors);
+        } else if (I.kind == RQ_INST_MBS && I.mbs) {
+            mix(I.mbs->months);
+        }
+    }
+    return h;
+}
+
+struct TuningCache {
+    std::mutex mu;
+    bool loaded = false;
+    std::vector<std::pair<uint64_t, rq_tuning>> entries;
+} g_tuning;
+
+const char *tuning_file() { return std::getenv("RQ_TUNING_CACHE"); }
+
+void tuning_load_locked()
+{
+    if (g_tuning.loaded) return;
+    g_tuning.loaded = true;
+    const char *path = tuning_file();
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    unsigned long long sig;
+    int c, w, o;
+    while (std::fscanf(f, "%llx %d %d %d", &sig, &c, &w, &o) == 4) {
+        if (c < 0 || c > 4096 || w < 0 || w > 32 || (o != RQ_ORDER_COST && o != RQ_ORDER_GIVEN)) continue;
+        g_tuning.entries.emplace_back((uint64_t)sig, rq_tuning{c, w, o});
+    }
+    std::fclose(f);
+}
+
+bool tuning_find(uint64_t sig, rq_tuning &out)
+{
+    std::lock_guard<std::mutex> lk(g_tuning.mu);
+    tuning_load_locked();
+    for (auto it = g_tuning.entries.rbegin(); it != g_tuning.entries.rend(); ++it)   // the latest wins
+        if (it->first == sig) {
+            out = it->second;
+            return true;
+        }
+    return false;
+}
+
+void tuning_store(uint64_t sig, const rq_tuning &t)
+{
+    std::lock_guard<std::mutex> lk(g_tuning.mu);
+    tuning_load_locked();
+    g_tuning.entries.emplace_back(sig, t);
+    const char *path = tuning_file();
+    if (!path || !*path) return;
+    if (FILE *f = std::fopen(path, "a")) {   // best effort: an unwritable file only loses persistence
+        std::fprintf(f, "%016llx %d %d %d\n", (unsigned long long)sig, t.chunk, t.waves_per_cu, t.order);
+        std::fclose(f);
+    }
+}
+
 rq_status run_batch(const rq_instrument *inst, int n_inst, rq_precision prec, bool greeks, const rq_tuning *tuning,
                     const rq_result *outs, const rq_result *grads, uint64_t *t_first, uint64_t *t_last, void *ws,
                     size_t ws_bytes, hipStream_t st)
 {
     rq_tuning tu{0, 0, RQ_ORDER_COST};
+    rq_tuning cached;
+    if (!tuning && inst && n_inst >= 1 && n_inst <= kBatchMaxInst &&
+        tuning_find(batch_signature(inst, n_inst, prec, greeks), cached))
+        tuning = &cached;
     if (tuning) {
         tu = *tuning;
         if (tu.chunk < 0 || tu.chunk > 4096) return fail(RQ_EINVAL, "tuning.chunk = %d outside [0, 4096]", tu.chunk);
@@ -1380,47 +1471,90 @@ rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision 
     const int occ = rq::batch_blocks_per_cu(prec == RQ_FP32, greeks, greeks ? 2 : 0);
     if (occ <= 0) return fail(RQ_EHIP, "occupancy query of the batch kernel failed");
     std::vector<rq_tuning> cand;
-    const int chunks[] = {1, 2, 4, 8};
+    const int chunks[] = {1, 2, 4, 8, 16};
     const int orders[] = {RQ_ORDER_COST, RQ_ORDER_GIVEN};
     std::vector<int> per_cu = {occ};
     if (occ > 1) per_cu.push_back(occ / 2);
     for (int o : orders)
         for (int pc : per_cu)
             for (int c : chunks) cand.push_back(rq_tuning{c, pc, o});
+    // a large batch is screened on a probe of itself: every instrument with
+    // its replications divided by a power of two (at least one), so that
+    // the probe holds about 2^28 paths; the three fastest shapes on the
+    // probe are then timed on the batch itself
+    double paths = 0.0;
+    for (int k = 0; k < n_inst; ++k) paths += (double)inst[k].N * (double)inst[k].M;
+    int div = 1;
+    while (paths / div > (double)(1 << 28) && div < 64) div *= 2;
+    std::vector<rq_instrument> probe(inst, inst + n_inst);
+    for (auto &I : probe) I.M = std::max(1, I.M / div);
     hipEvent_t e0, e1;
     RQ_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
         return fail(RQ_EHIP, "hipEventCreate failed");
     }
-    double bms = INFINITY;
-    rq_tuning bt = cand[0];
-    // one untimed run (first touch of the workspace, code load), then each
-    // candidate once
-    rq_status stt = run_batch(inst, n_inst, prec, greeks, &cand[0], outs, grads, nullptr, nullptr, ws, ws_bytes, st);
-    for (size_t c = 0; stt == RQ_OK && c < cand.size(); ++c) {
-        if (hipEventRecord(e0, st) != hipSuccess) {
-            stt = fail(RQ_EHIP, "hipEventRecord failed");
-            break;
-        }
-        stt = run_batch(inst, n_inst, prec, greeks, &cand[c], outs, grads, nullptr, nullptr, ws, ws_bytes, st);
-        if (stt != RQ_OK) break;
+    auto time_one = [&](const rq_instrument *list, const rq_tuning &t, double &ms_out) -> rq_status {
+        if (hipEventRecord(e0, st) != hipSuccess) return fail(RQ_EHIP, "hipEventRecord failed");
+        rq_status r = run_batch(list, n_inst, prec, greeks, &t, outs, grads, nullptr, nullptr, ws, ws_bytes, st);
+        if (r != RQ_OK) return r;
         float ms = 0.0f;
         if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            stt = fail(RQ_EHIP, "timing the batch failed");
-            break;
-        }
-        if (ms < bms) {
-            bms = ms;
-            bt = cand[c];
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return fail(RQ_EHIP, "timing the batch failed");
+        ms_out = ms;
+        return RQ_OK;
+    };
+    // one untimed run (first touch of the workspace, code load), then each
+    // candidate once on the probe (the batch itself when div = 1)
+    const rq_instrument *screen = div > 1 ? probe.data() : inst;
+    std::vector<std::pair<double, int>> timed;
+    double ms = 0.0;
+    rq_status stt = run_batch(screen, n_inst, prec, greeks, &cand[0], outs, grads, nullptr, nullptr, ws, ws_bytes, st);
+    for (size_t c = 0; stt == RQ_OK && c < cand.size(); ++c) {
+        stt = time_one(screen, cand[c], ms);
+        if (stt == RQ_OK) timed.emplace_back(ms, (int)c);
+    }
+    rq_tuning bt = cand[0];
+    double bms = INFINITY;
+    if (stt == RQ_OK) {
+        std::stable_sort(timed.begin(), timed.end());
+        if (div == 1) {
+            bt = cand[timed[0].second];
+            bms = timed[0].first;
+        } else {
+            // the finalists on the full batch, after one untimed full run
+            stt = run_batch(inst, n_inst, prec, greeks, &cand[timed[0].second], outs, grads, nullptr, nullptr, ws,
+                            ws_bytes, st);
+            for (size_t r = 0; stt == RQ_OK && r < std::min<size_t>(3, timed.size()); ++r) {
+                stt = time_one(inst, cand[timed[r].second], ms);
+                if (stt == RQ_OK && ms < bms) {
+                    bms = ms;
+                    bt = cand[timed[r].second];
+                }
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (stt != RQ_OK) return stt;
+    tuning_store(batch_signature(inst, n_inst, prec, greeks), bt);
     *best = bt;
     if (best_ms) *best_ms = bms;
+    return RQ_OK;
+}
+
+rq_status rq_batch_tuning(const rq_instrument *inst, int n_inst, rq_precision prec, int with_greeks,
+                          rq_tuning *out, int *from_autotuner)
+{
+    if (!out) return fail(RQ_EINVAL, "out is NULL");
+    BatchPlan bp;
+    rq_status s0 = plan_batch(inst, n_inst, prec, with_greeks != 0, RQ_ORDER_COST, bp);
+    if (s0) return s0;
+    rq_tuning t{0, 0, RQ_ORDER_COST};
+    const bool hit = tuning_find(batch_signature(inst, n_inst, prec, with_greeks != 0), t);
+    *out = hit ? t : rq_tuning{0, 0, RQ_ORDER_COST};
+    if (from_autotuner) *from_autotuner = hit ? 1 : 0;
     return RQ_OK;
 }
 

@@ -5,6 +5,7 @@ import ctypes as C
 import math
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -15,8 +16,8 @@ import rqmc_inputs as I
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    txt = open(os.path.join(ROOT, "include", "rqmc.h")).read()
+def _declared(header="rqmc.h"):
+    txt = open(os.path.join(ROOT, "include", header)).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(rq_[a-z0-9_]+)\s*\(", txt)))
 
@@ -24,10 +25,19 @@ def _declared():
 def test_library_exports_every_declared_symbol():
     lib = rq.lib()
     names = _declared()
-    assert {"rq_sequence", "rq_price_caplets", "rq_price_mbs", "rq_last_error"} <= set(names)
+    assert {"rq_sequence", "rq_price_caplets", "rq_price_mbs", "rq_last_error", "rq_batch_tuning"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
     assert "gfx950" in rq.version()
+
+
+def test_cpu_generator_library_exports_its_header():
+    lib = rq.cpu_lib()
+    names = _declared("rqmc_cpu.h")
+    assert {"rq_cpu_sequence", "rq_cpu_alg2_run", "rq_cpu_last_error", "rq_cpu_max_threads"} == set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert not any(hasattr(rq.lib(), n) for n in names)   # two libraries, nothing shared
 
 
 def test_workspace_sizes_and_validation():
@@ -171,3 +181,49 @@ def test_scheme_and_generator_flag_combinations():
     assert st == rq.RQ_EINVAL and "caplets" in rq.last_error()
     st = rq.lib().rq_sequence(4, 64, 1, 1, rq.LMM_EULER, 0, C.c_void_p(256), C.c_void_p(256), 1 << 20, None)
     assert st == rq.RQ_EINVAL
+
+
+def _fnv_signature(insts, prec, greeks):
+    # the batch signature as the library defines it (FNV-1a 64 over the
+    # little-endian bytes of each field), written again here
+    h = 0xcbf29ce484222325
+
+    def mix(v):
+        nonlocal h
+        for b in int(v).to_bytes(8, "little", signed=True):
+            h ^= b
+            h = (h * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+
+    mix(prec)
+    mix(1 if greeks else 0)
+    mix(len(insts))
+    for c in insts:
+        mix(0 if c.kind == "lmm" else 1)
+        mix(c.N)
+        mix(c.M)
+        mix(getattr(c, "flags", 0))
+        if c.kind == "lmm":
+            mix(c.model.n_fwd)
+            mix(c.model.n_factors)
+        else:
+            mix(c.model.months)
+    return h
+
+
+def test_batch_tuning_cache_file_is_read(tmp_path):
+    # a tuning kept in the RQ_TUNING_CACHE file by an earlier process is what
+    # price_batch would use for that list; another list stays automatic
+    import subprocess
+    insts = I.cfg5()[:5]
+    sig = _fnv_signature(insts, 1, True)
+    f = tmp_path / "tuning.txt"
+    f.write_text(f"{sig:016x} 4 3 1\n")
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1408_5526_amd as rq, rqmc_inputs as I\n"
+            "L = I.cfg5()\n"
+            "print(rq.batch_tuning(L[:5], 'fp32', greeks=True), rq.batch_tuning(L[:5], 'fp32', greeks=False),"
+            " rq.batch_tuning(L[:6], 'fp32', greeks=True))\n") % ROOT
+    env = dict(os.environ, RQ_TUNING_CACHE=str(f))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "((4, 3, 1), True) ((0, 0, 0), False) ((0, 0, 0), False)", out.stdout

@@ -171,12 +171,18 @@ def test_batch_timestamps_bracket_every_instrument():
 def test_autotune_picks_a_candidate_and_keeps_results():
     batch = _mixed()
     _say("autotune")
+    assert rq.batch_tuning(batch, precision="fp32", greeks=True) == ((0, 0, 0), False)
     (chunk, per_cu, order), ms = rq.autotune_batch(batch, precision="fp32", greeks=True)
-    assert chunk in (1, 2, 4, 8) and per_cu >= 1 and order in (rq.ORDER_COST, rq.ORDER_GIVEN) and ms > 0
+    assert chunk in (1, 2, 4, 8, 16) and per_cu >= 1 and order in (rq.ORDER_COST, rq.ORDER_GIVEN) and ms > 0
+    # kept for this list's signature: price_batch without a tuning uses it
+    assert rq.batch_tuning(batch, precision="fp32", greeks=True) == ((chunk, per_cu, order), True)
+    assert rq.batch_tuning(batch, precision="fp64", greeks=True)[1] is False
     a = rq.price_batch(batch, precision="fp32", greeks=True, tuning=(chunk, per_cu, order))
     b = rq.price_batch(batch, precision="fp32", greeks=True)
+    c = rq.price_batch(batch, precision="fp32", greeks=True, tuning=(1, 1, rq.ORDER_GIVEN))
     for k in range(len(batch)):
         assert np.array_equal(_np(a.results[k].theta), _np(b.results[k].theta))
+        assert np.array_equal(_np(a.results[k].theta), _np(c.results[k].theta))
 
 
 def test_batch_of_the_256_instrument_workload_scaled_down():
@@ -205,3 +211,53 @@ def test_batch_rejects_bad_instrument_before_launch():
     batch = [Ins("mbs", I.mbs_paper(12), 64, 1, 1), Ins("lmm", bad, 64, 1, 1)]
     with pytest.raises(rq.RqError, match="instrument 1"):
         rq.price_batch(batch)
+
+
+# As-drawn instruments of the 256-instrument workload, among them the
+# largest shapes it draws (N = 2^18 with M = 512): a 55-forward 2-factor
+# book, a 360-month pool, a 45-forward 3-factor book and a 240-month pool
+DRAWN = (131, 216, 188, 6)
+# sampled replications (m_global) compared with the oracle, which prices
+# one replication at the full N
+SAMPLED = {131: (511,), 216: (300,), 188: (0, 255, 511), 6: (0, 511)}
+
+
+def _drawn():
+    full = I.cfg5()
+    return [Ins(full[k].kind, full[k].model, full[k].N, full[k].M, full[k].seed) for k in DRAWN]
+
+
+def _oracle_rows(ins, ms):
+    f = O.price_caplets if ins.kind == "lmm" else O.price_mbs
+    return {m: f(ins.model, ins.N, 1, ins.seed, m_offset=m)[0] for m in ms}
+
+
+def test_batch_as_drawn_matches_oracle_on_sampled_replications():
+    batch = _drawn()
+    _say("cfg5 as drawn", [(b.kind, b.N, b.M) for b in batch])
+    b64 = rq.price_batch(batch, precision="fp64")
+    b32 = rq.price_batch(batch, precision="fp32", greeks=True)
+    for k, ins in zip(DRAWN, batch):
+        rows = _oracle_rows(ins, SAMPLED[k])
+        th64, th32 = _np(b64.results[DRAWN.index(k)].theta), _np(b32.results[DRAWN.index(k)].theta)
+        assert np.isfinite(th32).all() and np.isfinite(_np(b32.results[DRAWN.index(k)].greeks.theta)).all()
+        sc = _scale(ins)
+        for m, want in rows.items():
+            assert (np.abs(th64[m] - want) <= 1e-12 * (np.abs(want) + sc)).all(), (k, m)
+            live = np.abs(want) > 0
+            rel = np.abs(th32[m] - want)[live] / np.abs(want)[live]
+            _say("drawn", k, "m", m, "fp32 max rel", float(rel.max()))
+            assert rel.max() <= 1e-6, (k, m)
+
+
+def test_batch_as_drawn_greeks_equal_single_calls():
+    batch = _drawn()
+    _say("cfg5 as drawn greeks")
+    br = rq.price_batch(batch, precision="fp32", greeks=True)
+    for j, ins in enumerate(batch):
+        f = rq.price_caplets if ins.kind == "lmm" else rq.price_mbs
+        r = f(ins.model, ins.N, ins.M, ins.seed, precision="fp32", greeks=True)
+        for a, b in ((br.results[j].theta, r.theta), (br.results[j].greeks.theta, r.greeks.theta)):
+            a, b = _np(a), _np(b)
+            scale = np.abs(b).max(axis=1, keepdims=True) + 1e-300
+            assert (np.abs(a - b) <= 1e-13 * scale).all(), (DRAWN[j], float((np.abs(a - b) / scale).max()))
