@@ -30,20 +30,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic work per path of the 80-forward, 3-factor book (flops: FMA = 2,
-# add/mul = 1, each special function = 1): 3,240 forward-steps x 26, 240
-# inverse normals x 32, 80 payoffs x 12, 240 point divisions.
-FLOPS_PER_PATH_LMM80 = 93_040
-# Price + 161 Greeks per path: the forward pass above, then for each of the
-# 3,240 forward-steps in reverse (48 flops): the pre-step state and drift
-# factor from the stored step-final w (11), the suffix sum of the w adjoint,
-# the drift-factor adjoint and its derivative, the vega terms and rewinding
-# w (37); and the adjoint of the 80 payoffs (20 each).
-FLOPS_PER_PATH_LMM80_GREEKS = 93_040 + 3_240 * 48 + 80 * 20
-# The adjoint runs as two kernels: the forward passes (no payoffs) and the
+# Work per path of the 80-forward, 3-factor book, counted from the kernels'
+# arithmetic as written (flops: FMA = 2, add/sub/mul = 1, each special
+# function = 1, FP32 and FP64 alike; integer digit work not counted):
+#  * forward-step (3,240 per path): drift factor 1/(1 + kappa 2^-X) (exp2,
+#    FMA, rcp: 4), w += g delta a (3 FMA: 6), the increment
+#    log2(e)(c + a.w) (3 FMA: 6), the state add (1): 17;
+#  * coordinate (240): the point R RN(1/P) (1), the FP32 inverse normal's
+#    main branch (u(1-u): 2, log: 1, FMA: 2, 2u-1: 2, t: 1, 9 FMA: 18,
+#    product: 1 = 27): 28;
+#  * payoff (80, pricing kernel): 2^X and the fixing value (2), 1 + delta L
+#    (2), L - K (1), numeraire product (1), Newton reciprocal (rcp and 4
+#    FMA: 9), delta (L - K) / num times the caplet flag (3), the book (1): 19;
+#  * reverse forward-step (3,240, adjoint): P = log2(e) a.w (mul, 2 FMA: 5),
+#    the pre-step state X - (P + c) (2), the drift factor (4), Wbar +=
+#    Xbar log2(e) a (3 FMA: 6), delta a.Wbar (mul, 2 FMA: 5), h = g (delta
+#    a.Wbar) (1), the vega entry (2 FMA, add: 5), Xbar += ln2 h (1 - g)
+#    (2 FMA: 4), the w rewind (3 FMA: 6): 38;
+#  * payoff section of the reverse kernel (80): the book over a common
+#    denominator (10), the payoffs again with their adjoint (27), the delta
+#    and vega outputs (4): 41.
+FLOPS_FWD_STEP, FLOPS_COORD, FLOPS_PAYOFF, FLOPS_REV_STEP, FLOPS_PAYOFF_ADJ = 17, 28, 19, 38, 41
+N_FS, N_COORD, N_FWD = 3_240, 240, 80
+FLOPS_PER_PATH_LMM80 = N_FS * FLOPS_FWD_STEP + N_COORD * FLOPS_COORD + N_FWD * FLOPS_PAYOFF
+# The adjoint's two kernels: the forward passes (no payoffs), then the
 # payoffs with the reverse sweep.
-FLOPS_PER_PATH_LMM80_FWD = 93_040 - 80 * 12
-FLOPS_PER_PATH_LMM80_REV = 80 * 12 + 3_240 * 48 + 80 * 20
+FLOPS_PER_PATH_LMM80_FWD = N_FS * FLOPS_FWD_STEP + N_COORD * FLOPS_COORD
+FLOPS_PER_PATH_LMM80_REV = N_FS * FLOPS_REV_STEP + N_FWD * FLOPS_PAYOFF_ADJ
+FLOPS_PER_PATH_LMM80_GREEKS = FLOPS_PER_PATH_LMM80_FWD + FLOPS_PER_PATH_LMM80_REV
+# The survey's algorithmic count of the textbook scheme (26 flops per
+# forward-step, 32 per inverse normal, 12 per payoff, one division per
+# point), reported beside the as-written count for the pricing kernel.
+FLOPS_PER_PATH_LMM80_SURVEY = 93_040
 N_GREEKS_LMM80 = 2 * 80 + 1
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}   # MI355X vector peaks (published)
 
@@ -77,6 +95,31 @@ def _traffic_bytes(profile: str, sources):
             return None
         return (float(kv["fetch_kib"]) * float(kv["fetch_factor"]) +
                 float(kv["write_kib"]) * float(kv["write_factor"])) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _executed_flops(profile: str, sources):
+    """FLOP-type instructions one launch of a kernel executed, from a
+    committed rocprofv3 counter run (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_{F32,
+    F64} per dispatch): 64 lanes x (ADD + MUL + 2 FMA + TRANS), every lane
+    counted -- or None when there is none or the kernel source has changed
+    since."""
+    path = os.path.join(ROOT, "profiles", profile)
+    try:
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if line.strip() and not line.startswith("#"):
+                    k, v = line.split()
+                    kv[k] = v
+        if kv.get("source_hash") != _kernel_source_hash(sources):
+            return None
+        tot = 0.0
+        for prec in ("F32", "F64"):
+            tot += float(kv[f"SQ_INSTS_VALU_ADD_{prec}"]) + float(kv[f"SQ_INSTS_VALU_MUL_{prec}"])
+            tot += 2.0 * float(kv[f"SQ_INSTS_VALU_FMA_{prec}"]) + float(kv[f"SQ_INSTS_VALU_TRANS_{prec}"])
+        return 64.0 * tot
     except (OSError, KeyError, ValueError):
         return None
 
@@ -168,6 +211,31 @@ def cpu_generator_baseline():
             "sample": f"Algorithm 2, {count} consecutive terms in each of 240 bases, {dt:.2f} s"}
 
 
+def cpu_simd_generator():
+    """The recursive generator built as a CPU baseline (librqmc_cpu.so:
+    Algorithm 2 on exact integer partial sums, blocks of low digits in SIMD
+    lanes, OpenMP over (replication, index range)), producing the same
+    [M][N][s] FP64 points as the GPU leg: all host threads on the GPU leg's
+    shape, and one thread on one replication of it."""
+    import numpy as np
+    import paper_1408_5526_amd as rq
+    s, n, m = 240, 1 << 16, 16
+    out = np.empty((m, n, s), dtype=np.float64)
+    rq.cpu_sequence(s, n, 1, 5, out=out)                 # first touch of the pages
+    rq.cpu_sequence(s, n, m, 5, out=out)
+    t0 = time.perf_counter()
+    rq.cpu_sequence(s, n, m, 5, out=out)
+    dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    rq.cpu_sequence(s, n, 1, 5, threads=1, out=out)
+    dt1 = time.perf_counter() - t1
+    return {"value": s * n * m / dt / 1e9, "unit": "GNumbers/s", "cores": rq.cpu_max_threads(),
+            "kind": "recursive generator (Algorithm 2), multi-core SIMD",
+            "sample": f"s = {s}, N = 2^16, M = {m} FP64 points ([M][N][s]), {dt:.2f} s",
+            "value_1core": s * n / dt1 / 1e9, "sample_1core": f"M = 1 on one thread, {dt1:.2f} s",
+            "cpu_model": _cpu_model()}
+
+
 def mbs_leg(rq, I, torch, dev, steps: int):
     """The 360-month MBS pool (s = 360, N = 2^14, M = 64): paths/s in FP64 and
     FP32 (and FP32 with the pathwise dPV/di0), and the paper's efficiency
@@ -227,10 +295,12 @@ def cpu_mbs_baseline():
             "sample": f"{m_sub} of the {c.M} replications at full N = {c.N}, FP64, {dt:.1f} s"}
 
 
-def batch_leg(rq, I, torch, dev, n_cap: int, m_cap: int, steps: int):
+def batch_leg(rq, I, torch, dev, n_cap: int, m_cap: int, steps: int, autotune: bool = True):
     """The 256-instrument batch (FP32 prices + Greeks) in one persistent
-    launch: whole-batch paths/s and the per-instrument completion times
-    (from the batch start) and spans, from the device real-time counter."""
+    launch: the autotuner picks the launch shape for the list (kept for its
+    signature, so the timed calls pass no tuning), then whole-batch paths/s
+    and the per-instrument completion times (from the batch start) and
+    spans, from the device real-time counter."""
     import numpy as np
     insts = I.cfg5()
     if n_cap or m_cap:
@@ -238,6 +308,16 @@ def batch_leg(rq, I, torch, dev, n_cap: int, m_cap: int, steps: int):
         insts = [dataclasses.replace(c, N=min(c.N, n_cap or c.N), M=min(c.M, m_cap or c.M)) for c in insts]
     paths = sum(c.N * c.M for c in insts)
     ws = torch.empty(rq.batch_workspace(insts, "fp32", greeks=True), dtype=torch.uint8, device=dev)
+    tune = {}
+    if autotune:
+        t0 = time.perf_counter()
+        (chunk, per_cu, order), tms = rq.autotune_batch(insts, "fp32", greeks=True, device=dev, ws=ws)
+        tune = {"chunk": chunk, "waves_per_cu": per_cu,
+                "order": "cost" if order == rq.ORDER_COST else "given",
+                "autotune_ms": tms, "autotune_wall_s": time.perf_counter() - t0}
+    used, from_tuner = rq.batch_tuning(insts, "fp32", greeks=True)
+    tune["used_by_price_batch"] = {"chunk": used[0], "waves_per_cu": used[1], "order": used[2],
+                                   "from_autotuner": from_tuner}
     rq.price_batch(insts, "fp32", greeks=True, device=dev, ws=ws)   # warm-up
     torch.cuda.synchronize()
     walls, br = [], None
@@ -254,6 +334,7 @@ def batch_leg(rq, I, torch, dev, n_cap: int, m_cap: int, steps: int):
     wall = float(np.median(walls))
     return {"workload": "cfg5_256_instruments" + ("" if not (n_cap or m_cap) else f"_N<=2^{n_cap.bit_length() - 1}_M<={m_cap}"),
             "n_instruments": len(insts), "paths": paths, "precision": "fp32", "greeks": True,
+            "tuning": tune,
             "paths_per_s": paths / wall, "ms_per_batch": wall * 1e3,
             "kernel_span_ms": float((tl.max() - tf.min()) / hz * 1e3),
             "completion_ms_p50": float(np.percentile(done, 50)), "completion_ms_p99": float(np.percentile(done, 99)),
@@ -269,8 +350,10 @@ def main(argv=None):
     ap.add_argument("--skip-fp64", action="store_true", help="do not time the FP64 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-m-per-core", type=int, default=4)
-    ap.add_argument("--batch", default="capped", choices=["capped", "full", "off"],
-                    help="256-instrument batch leg: N <= 2^14 and M <= 64 (capped), as drawn (full), or none")
+    ap.add_argument("--batch", default="full", choices=["capped", "full", "off"],
+                    help="256-instrument batch leg: as drawn (full), N <= 2^14 and M <= 64 (capped), or none")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="batch leg: skip the autotuner (automatic launch shape)")
     ap.add_argument("--no-generators", dest="generators", action="store_false",
                     help="skip the point-generation leg")
     ap.add_argument("--no-mbs", dest="mbs", action="store_false", help="skip the MBS leg")
@@ -322,10 +405,22 @@ def main(argv=None):
     if not args.skip_fp64 and head != "fp64":
         ms64, kms64, res64 = _time_steps(step("fp64"), args.steps, args.warmup)
         rq64, se64 = res64.mean[-1].item(), res64.se[-1].item()
+        # the like-for-like comparison: FP64 prices + the same 161 Greeks
+        wsg64 = torch.empty(rq.caplets_workspace(model, N, M, 0, "fp64", greeks=True), dtype=torch.uint8,
+                            device=dev)
+        ms64g, kms64g, res64g = _time_steps(
+            lambda: rq.price_caplets(model, N, M, seed, precision="fp64", greeks=True, device=dev, ws=wsg64),
+            args.steps, args.warmup)
+        del wsg64
         out_extra = {
             "fp64_paths_per_s": N * M / (ms64 / 1e3),
             "fp64_ms_per_step": ms64,
             "fp64_kernel_ms": kms64,
+            "fp64_greeks_paths_per_s": N * M / (ms64g / 1e3),
+            "fp64_greeks_ms_per_step": ms64g,
+            "speedup_vs_fp64_greeks": ms64g / ms_g,
+            "fp64_greeks_vs_fp32_greeks_max_rel": float(
+                ((res64g.greeks.mean - res_g.greeks.mean).abs().max() / res64g.greeks.mean.abs().max()).item()),
             "speedup_vs_fp64": ms64 / ms_g,
             "book_rq": {"fp32_greeks": res_g.mean[-1].item(), "fp32": res.mean[-1].item(), "fp64": rq64},
             "book_se": {"fp32_greeks": res_g.se[-1].item(), "fp32": res.se[-1].item(), "fp64": se64},
@@ -354,6 +449,9 @@ def main(argv=None):
     out_extra["prices_only_fp32"] = {
         "paths_per_s": N * M / (ms / 1e3), "ms_per_step": ms, "kernel_ms": kms,
         "achieved_tflops": FLOPS_PER_PATH_LMM80 * N * M / (kms / 1e3) / 1e12,
+        "flops_per_path": FLOPS_PER_PATH_LMM80,
+        "achieved_tflops_survey_count": FLOPS_PER_PATH_LMM80_SURVEY * N * M / (kms / 1e3) / 1e12,
+        "flops_per_path_survey": FLOPS_PER_PATH_LMM80_SURVEY,
         "traffic": _traffic_bytes("lmm80_3f_fp32_traffic.txt", PRICE_SOURCES)}
 
     dtype = "f32"
@@ -364,6 +462,10 @@ def main(argv=None):
     paths_timed = N * M * args.steps
     achieved = FLOPS_PER_PATH_LMM80_REV * paths_timed / (rev_ms / 1e3) / 1e12
     achieved_fwd = FLOPS_PER_PATH_LMM80_FWD * paths_timed / (fwd_ms / 1e3) / 1e12
+    rev_launch_s = rev_ms / max(rev_n, 1) / 1e3
+    fwd_launch_s = fwd_ms / max(fwd_n, 1) / 1e3
+    ex_rev = _executed_flops("lmm80_3f_fp32_greeks_rev_flops.txt", ADJ_SOURCES)
+    ex_fwd = _executed_flops("lmm80_3f_fp32_greeks_fwd_flops.txt", ADJ_SOURCES)
     line = {
         "metric": "RQMC paths/s + Greeks/s (LMM 80-fwd caplets) vs plain FP64, at equal std err",
         "value": N * M / (ms_g / 1e3),
@@ -386,20 +488,25 @@ def main(argv=None):
                      "traffic": _traffic_bytes("lmm80_3f_fp32_greeks_rev_traffic.txt", ADJ_SOURCES),
                      "kernel": "lmm_adj_rev_kernel<80,3,float,false>", "kernel_ms": rev_ms / max(rev_n, 1),
                      "launches_per_step": rev_n / args.steps,
-                     "flops_per_path": FLOPS_PER_PATH_LMM80_REV},
+                     "flops_per_path": FLOPS_PER_PATH_LMM80_REV, "flops_basis": "kernel arithmetic as written",
+                     "executed": ex_rev / rev_launch_s / 1e12 if ex_rev else None,
+                     "executed_frac": ex_rev / rev_launch_s / 1e12 / peak if ex_rev else None,
+                     "peak_single_issue": 78.6},
         "roofline_fwd": {"bound": "alu", "achieved": achieved_fwd, "peak": peak, "unit": "TFLOP/s",
                          "frac": achieved_fwd / peak,
                          "traffic": _traffic_bytes("lmm80_3f_fp32_greeks_fwd_traffic.txt", ADJ_SOURCES),
                          "kernel": "lmm_adj_fwd_kernel<80,3,float,false>", "kernel_ms": fwd_ms / max(fwd_n, 1),
                          "launches_per_step": fwd_n / args.steps,
-                         "flops_per_path": FLOPS_PER_PATH_LMM80_FWD},
+                         "flops_per_path": FLOPS_PER_PATH_LMM80_FWD, "flops_basis": "kernel arithmetic as written",
+                         "executed": ex_fwd / fwd_launch_s / 1e12 if ex_fwd else None,
+                         "executed_frac": ex_fwd / fwd_launch_s / 1e12 / peak if ex_fwd else None},
         "adjoint_pass": {"kernel_ms": kms_g, "flops_per_path": FLOPS_PER_PATH_LMM80_GREEKS,
                          "achieved": FLOPS_PER_PATH_LMM80_GREEKS * N * M / (kms_g / 1e3) / 1e12},
     }
     line.update(out_extra)
     if args.batch != "off":
         caps = (1 << 14, 64) if args.batch == "capped" else (0, 0)
-        line["batch"] = batch_leg(rq, I, torch, dev, caps[0], caps[1], 3)
+        line["batch"] = batch_leg(rq, I, torch, dev, caps[0], caps[1], 3, args.autotune)
     if args.generators:
         line["generators"] = generator_leg(rq, torch, dev, 3)
     if args.mbs:
@@ -409,6 +516,7 @@ def main(argv=None):
         line["cpu_baseline"] = cpu_baseline(model, N, seed, args.cpu_m_per_core)
         if args.generators:
             line["generators"]["cpu_recursive"] = cpu_generator_baseline()
+            line["generators"]["cpu_recursive_simd"] = cpu_simd_generator()
         if args.mbs:
             line["mbs"]["cpu_baseline"] = cpu_mbs_baseline()
     print(json.dumps(line), flush=True)

@@ -24,7 +24,7 @@
 //   Xbar_n += h ln2 (1 - g_n)             (delta a_n . Wbar G'(X_n), G' = ln2 G (1 - G))
 //   w    -= g_n delta a_n                 (back to w_{n-1})
 // with a_n = sigma_n b_n.  The lane accumulates sigma_n vega_n,
-//   sigma_n vega_n += Xbar_n (P - 2 log2(e) c_n) + h,
+//   sigma_n vega_n += Xbar_n (P + 2 log2(e) c_n) + h,   (c_n = -delta |a_n|^2 / 2)
 // so that the one dot product P serves the state and the vega, and h both
 // the vega and Xbar with constant factors; the sums are divided by sigma_n
 // once, in FP64, at the end (a zero sigma_n is carried as 2^-60).
