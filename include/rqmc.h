@@ -215,6 +215,30 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
  * row are the same in any chunk).  Set it before sizing the workspace. */
 rq_status rq_set_adjoint_store_limit(size_t bytes);
 
+/* price_caplets_noalloc: rq_price_caplets without a caller workspace, for
+ * callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, hosts that forbid allocation during a run).  It
+ * allocates nothing: the workspace is a fixed device array of
+ * RQ_NOALLOC_SCRATCH_BYTES (64 MiB) inside the library, one per GPU, held
+ * until the process ends; its address on the current device is looked up
+ * on the first call there.  Arguments, outputs and results are those of
+ * rq_price_caplets with the same arguments (same kernels); with grad the
+ * adjoint's store region takes whatever the tables and partial sums leave
+ * of the array, in as many chunks as that needs.
+ * Errors: as rq_price_caplets, plus RQ_ERANGE when the tables and partial
+ * sums (M * ceil(N / 256) * (n_fwd + 1) doubles without Greeks,
+ * M * ceil(N / 64) * (3 n_fwd + 2) with them), plus one stored 64-path
+ * task with Greeks, do not fit the array; nothing is launched then.
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one
+ * GPU (other streams, other host threads) race and must be serialised by
+ * the caller.  The array keeps the last call's contents; each call writes
+ * every byte it later reads. */
+#define RQ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rq_status rq_price_caplets_noalloc(const rq_lmm_model *model, int64_t N, int M, uint64_t seed,
+                                   int64_t m_offset, int flags, rq_precision prec,
+                                   const rq_result *out, const rq_result *grad, double *per_path,
+                                   void *stream);
+
 /* price_mbs(params, N, M): present value of the mortgage pool.
  *   grad  NULL, or the pathwise total derivative dPV/di0 (one output per
  *         replication; rates scale with i0 and the payment c and the

@@ -96,6 +96,10 @@ def lib():
     L.rq_price_caplets.argtypes = [C.POINTER(rq_lmm_model), C.c_int64, C.c_int, C.c_uint64, C.c_int64,
                                    C.c_int, C.c_int, C.POINTER(rq_result), C.POINTER(rq_result),
                                    C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]
+    L.rq_price_caplets_noalloc.restype = C.c_int
+    L.rq_price_caplets_noalloc.argtypes = [C.POINTER(rq_lmm_model), C.c_int64, C.c_int, C.c_uint64, C.c_int64,
+                                           C.c_int, C.c_int, C.POINTER(rq_result), C.POINTER(rq_result),
+                                           C.c_void_p, C.c_void_p]
     L.rq_price_mbs.restype = C.c_int
     L.rq_price_mbs.argtypes = [C.POINTER(rq_mbs_params), C.c_int64, C.c_int, C.c_uint64, C.c_int64,
                                C.c_int, C.c_int, C.POINTER(rq_result), C.POINTER(rq_result),
@@ -272,6 +276,26 @@ def price_caplets(model, N: int, M: int, seed: int, m_offset: int = 0, flags: in
                                   C.c_void_p(pp.data_ptr() if pp is not None else 0),
                                   C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)))
     res.per_path = pp
+    res.greeks = gres
+    return res
+
+
+def price_caplets_noalloc(model, N: int, M: int, seed: int, m_offset: int = 0, flags: int = 0,
+                          precision="fp64", greeks: bool = False, out=None, grad=None,
+                          device=None) -> Result:
+    """price_caplets on the library's own device scratch array (no
+    workspace; RQ_ERANGE beyond its size).  out / grad: optional
+    preallocated (Result, rq_result) pairs from a previous call, so that a
+    caller can run with no allocation at all."""
+    dev = _device(device)
+    h = _LmmHost(model)
+    res, c = out if out is not None else _result(M, model.n_fwd + 1, dev)
+    if greeks:
+        gres, gc = grad if grad is not None else _result(M, 2 * model.n_fwd + 1, dev)
+    else:
+        gres, gc = None, None
+    _check(lib().rq_price_caplets_noalloc(C.byref(h.c), N, M, seed, m_offset, flags, _prec(precision),
+                                          C.byref(c), C.byref(gc) if greeks else None, None, _stream(dev)))
     res.greeks = gres
     return res
 

@@ -17,6 +17,13 @@
 #include "../../include/rqmc.h"
 #include "rq_internal.h"
 
+// Device scratch of rq_price_caplets_noalloc: one copy per GPU, held until
+// the process ends.  Host code never passes this name to a kernel or a copy
+// (on the host it is only a stand-in for the symbol); it uses the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = RQ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 using rq::BaseEnt;
@@ -41,6 +48,14 @@ rq_status fail(rq_status st, const char *fmt, ...)
         if (e_ != hipSuccess)                                                          \
             return fail(RQ_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
     } while (0)
+
+// The scratch array's device address per device, looked up once per device
+// (with that device current) by the first no-allocation call on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+rq_status scratch_of_device(void *&ws, size_t &ws_bytes);
 
 // Optional kernel timer (rq_timer_begin / rq_timer_end).
 // The adjoint's store region per chunk (single calls) or window (batch),
@@ -84,6 +99,24 @@ struct TimedRegion {
         }
     }
 };
+
+rq_status scratch_of_device(void *&ws, size_t &ws_bytes)
+{
+    int dev = -1;
+    RQ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(RQ_EUNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RQ_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    ws = g_scratch_ptr[dev];
+    ws_bytes = kScratchBytes;
+    return RQ_OK;
+}
 
 // The first RQ_MAX_DIM primes (sieve of Eratosthenes).
 const std::vector<uint32_t> &primes()
@@ -1173,23 +1206,24 @@ static size_t adj_task_elems(const rq_lmm_model *model)
     const int nfc = (model->n_fwd + 15) / 16 * 16;
     return adj_w_elems(model) + (size_t)nfc * rq::kAdjBlockHost;
 }
-static size_t adj_store_bytes(const rq_lmm_model *model, int64_t tasks)
+static size_t adj_store_bytes(const rq_lmm_model *model, int64_t tasks, size_t limit)
 {
     const size_t per = adj_task_elems(model) * sizeof(double);
-    const int64_t fit = std::max<int64_t>(1, (int64_t)(g_adj_store_limit.load() / per));
+    const int64_t fit = std::max<int64_t>(1, (int64_t)(limit / per));
     return (size_t)std::min<int64_t>(tasks, fit) * per;
 }
-static int64_t adj_chunk(const rq_lmm_model *model, int64_t tasks, size_t elem)
+static int64_t adj_chunk(const rq_lmm_model *model, int64_t tasks, size_t elem, size_t limit)
 {
-    const int64_t fit = std::max<int64_t>(1, (int64_t)(adj_store_bytes(model, tasks) / (adj_task_elems(model) * elem)));
+    const int64_t fit =
+        std::max<int64_t>(1, (int64_t)(adj_store_bytes(model, tasks, limit) / (adj_task_elems(model) * elem)));
     const int64_t n_chunks = (tasks + fit - 1) / fit;
     return (tasks + n_chunks - 1) / n_chunks;   // equal chunks, the last one at most as large
 }
 
 // Model-region bytes and partial-region bytes of a LIBOR call; with Greeks
 // the byte offset of the adjoint's store region inside the partial region.
-static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greeks, size_t &mb, size_t &pb,
-                         int &n_blk, size_t *wtop_off = nullptr)
+static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greeks, size_t store_limit, size_t &mb,
+                         size_t &pb, int &n_blk, size_t *wtop_off = nullptr)
 {
     const int rows = lmm_rows(model->n_fwd);
     const int n_out = model->n_fwd + 1;
@@ -1200,7 +1234,7 @@ static void caplet_sizes(const rq_lmm_model *model, int64_t N, int M, bool greek
         n_blk = adj_blocks(N);
         pb = al((size_t)M * n_blk * (n_out + n_g) * sizeof(double));
         if (wtop_off) *wtop_off = pb;
-        pb += adj_store_bytes(model, (int64_t)M * n_blk) + 256;   // + room to align the state rows
+        pb += adj_store_bytes(model, (int64_t)M * n_blk, store_limit) + 256;   // + room to align the state rows
     } else {
         n_blk = lmm_blocks(N);
         pb = (size_t)M * n_blk * n_out * sizeof(double);
@@ -1223,13 +1257,20 @@ size_t rq_caplets_workspace(const rq_lmm_model *model, int64_t N, int M, int fla
     (void)prec;
     size_t mb, pb;
     int n_blk;
-    caplet_sizes(model, N, M, with_greeks != 0, mb, pb, n_blk);
+    caplet_sizes(model, N, M, with_greeks != 0, g_adj_store_limit.load(), mb, pb, n_blk);
     return layout(s, g, M, flags, mb, pb).total;
 }
 
-rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t seed, int64_t m_offset,
-                           int flags, rq_precision prec, const rq_result *out, const rq_result *grad,
-                           double *per_path, void *ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+// The LIBOR entry point's body.  ws == nullptr selects the library's own
+// scratch array of the current device (rq_price_caplets_noalloc): the store
+// region of the adjoint is then cut to what fits beside the other regions.
+rq_status price_caplets_impl(const rq_lmm_model *model, int64_t N, int M, uint64_t seed, int64_t m_offset,
+                             int flags, rq_precision prec, const rq_result *out, const rq_result *grad,
+                             double *per_path, void *ws, size_t ws_bytes, hipStream_t st)
 {
     rq_status stt = check_lmm(model);
     if (stt) return stt;
@@ -1247,7 +1288,23 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     const bool greeks = grad != nullptr;
     size_t mb, pb, wtop_off = 0;
     int n_blk;
-    caplet_sizes(model, N, M, greeks, mb, pb, n_blk, &wtop_off);
+    size_t store_limit = g_adj_store_limit.load();
+    const bool own = ws == nullptr;
+    if (own) {
+        if ((stt = scratch_of_device(ws, ws_bytes))) return stt;
+        if (greeks) {   // the store region takes what the other regions leave
+            caplet_sizes(model, N, M, true, 0, mb, pb, n_blk, &wtop_off);   // room for one task
+            const size_t one = adj_task_elems(model) * sizeof(double);
+            const size_t fixed = layout(s, g, M, flags, mb, pb - one).total;
+            if (fixed + one > ws_bytes)
+                return fail(RQ_ERANGE,
+                            "rq_price_caplets_noalloc: %zu bytes of tables and partial sums plus %zu bytes per "
+                            "stored 64-path task exceed the %zu-byte scratch array",
+                            fixed, one, ws_bytes);
+            store_limit = std::min(store_limit, (ws_bytes - fixed) / one * one);
+        }
+    }
+    caplet_sizes(model, N, M, greeks, store_limit, mb, pb, n_blk, &wtop_off);
     const int n_out = model->n_fwd + 1;
     const int n_g = 2 * model->n_fwd + 1;
     if ((int64_t)n_blk * M >= (1ll << 31)) return fail(RQ_ERANGE, "N*M too large for one launch");
@@ -1259,10 +1316,12 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     }
     tab.resize(mb, 0);
     const Layout L = layout(s, g, M, flags, mb, pb);
+    if (own && L.total > ws_bytes)
+        return fail(RQ_ERANGE, "rq_price_caplets_noalloc: %zu bytes of tables and partial sums exceed the %zu-byte "
+                               "scratch array", L.total, ws_bytes);
     if ((stt = check_ws(ws, ws_bytes, L.total))) return stt;
     PointTables pt;
     if ((stt = build_point_tables(s, g, seed, flags, pt))) return stt;
-    hipStream_t st = (hipStream_t)stream;
     uint8_t *w = (uint8_t *)ws;
     if ((stt = stage_and_setup(pt, tab, L, g, s, M, seed, m_offset, flags, w, st))) return stt;
     rq::LmmArgs a;
@@ -1272,7 +1331,7 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     a.adj = greeks ? (const void *)(w + L.model + adj_off) : nullptr;
     const int64_t tasks = (int64_t)M * n_blk;
     const size_t elem = prec == RQ_FP32 ? sizeof(float) : sizeof(double);
-    const int64_t chunk = greeks ? adj_chunk(model, tasks, elem) : 0;
+    const int64_t chunk = greeks ? adj_chunk(model, tasks, elem, store_limit) : 0;
     a.wtop = greeks ? (void *)(w + L.partial + wtop_off) : nullptr;
     a.xs = greeks ? (void *)(w + L.partial + wtop_off + al((size_t)chunk * adj_w_elems(model) * elem)) : nullptr;
     a.n_slots = 0;
@@ -1312,6 +1371,27 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
     if ((stt = finish(out, a.partial, n_out, 0, M, n_blk, n_out, N, st))) return stt;
     if (greeks) return finish(grad, a.partial_g, n_g, 0, M, n_blk, n_g, N, st);
     return RQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t seed, int64_t m_offset,
+                           int flags, rq_precision prec, const rq_result *out, const rq_result *grad,
+                           double *per_path, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ws) return fail(RQ_EINVAL, "workspace pointer is NULL");
+    return price_caplets_impl(model, N, M, seed, m_offset, flags, prec, out, grad, per_path, ws, ws_bytes,
+                              (hipStream_t)stream);
+}
+
+rq_status rq_price_caplets_noalloc(const rq_lmm_model *model, int64_t N, int M, uint64_t seed, int64_t m_offset,
+                                   int flags, rq_precision prec, const rq_result *out, const rq_result *grad,
+                                   double *per_path, void *stream)
+{
+    return price_caplets_impl(model, N, M, seed, m_offset, flags, prec, out, grad, per_path, nullptr, 0,
+                              (hipStream_t)stream);
 }
 
 size_t rq_mbs_workspace(const rq_mbs_params *params, int64_t N, int M, int flags, rq_precision prec,
