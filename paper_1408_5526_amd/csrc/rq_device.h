@@ -277,6 +277,32 @@ __device__ __forceinline__ float inv_normal(double u, float)
 // ---------------------------------------------------------------------------
 // Elementary functions of the path arithmetic in the two precisions.
 // ---------------------------------------------------------------------------
+// 2^x in FP64 for the adjoint's FP64 form (its drift factor and fixing
+// values): with k = rint(x), 2^x = e^r 2^k, r = (x - k) ln 2 (x - k is exact
+// and its product with RN(ln 2) is within an ulp of r, |r| <= ln2 / 2); e^r
+// by the Taylor polynomial of degree 12 (truncation below 2^-53 relative)
+// in Horner form.  Within about two ulps (checked against 50-digit values
+// when the constants were chosen).  Arguments are clamped to [-1020, 1020],
+// where 2^x stays a normal number.
+__device__ __forceinline__ double exp2_f64(double x)
+{
+    x = __builtin_fmin(__builtin_fmax(x, -1020.0), 1020.0);
+    const double k = __builtin_rint(x);
+    const double r = (x - k) * 0x1.62e42fefa39efp-1;
+    double p = 0x1.1eed8eff8d898p-29;   // 1/12!
+    p = __builtin_fma(p, r, 0x1.ae64567f544e4p-26);
+    p = __builtin_fma(p, r, 0x1.27e4fb7789f5cp-22);
+    p = __builtin_fma(p, r, 0x1.71de3a556c734p-19);
+    p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-16);
+    p = __builtin_fma(p, r, 0x1.a01a01a01a01ap-13);
+    p = __builtin_fma(p, r, 0x1.6c16c16c16c17p-10);
+    p = __builtin_fma(p, r, 0x1.1111111111111p-7);
+    p = __builtin_fma(p, r, 0x1.5555555555555p-5);
+    p = __builtin_fma(p, r, 0x1.5555555555555p-3);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    return __builtin_ldexp(__builtin_fma(p, r, 1.0), (int)k);
+}
 __device__ __forceinline__ double fexp(double x) { return exp(x); }
 __device__ __forceinline__ float fexp(float x) { return __expf(x); }
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }

@@ -45,8 +45,14 @@ namespace rq {
 // pseudo-random points (the comparison baseline).  EULER: the plain Euler
 // step of the paper's discretised SDE instead of the log-Euler step,
 //   L_n <- L_n + mu_n L_n delta + L_n sqrt(delta) a_n . z_k = L_n (1 + a_n . w).
+// Occupancy hints: FP32 Halton forms at four waves per SIMD; FP64 Halton
+// forms at two (256 registers: the 80 FP64 forwards take 160 of them, and
+// the second wave hides the latency of the long dependent FP64 chains of
+// the drift factor, the exponential and the digits); Philox forms at the
+// compiler's choice.
 template <int NFC, int D, typename T, int GEN, bool EULER = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && GEN != 2 ? 4 : 1)))
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(GEN == 2 ? 1 : (sizeof(T) == 4 ? 4 : 2))))
 void lmm_kernel(LmmArgs a)
 {
     static_assert(NFC % 16 == 0, "capacity must be a multiple of 16");
@@ -128,8 +134,10 @@ void lmm_kernel(LmmArgs a)
                     X[n] += e;
                 }
             } else {
+                // drift factor delta L / (1 + delta L) with the Newton
+                // reciprocal (within an ulp or two of the quotient)
                 const double dl = delta * X[n];
-                const double g = dl / (1.0 + dl);
+                const double g = dl * recip64(1.0 + dl);
 #pragma unroll
                 for (int f = 0; f < D; ++f) w[f] = ffma(g, r64(n, 3 + f), w[f]);
                 if constexpr (EULER) {   // plain Euler: L <- L + L (a_n . w)

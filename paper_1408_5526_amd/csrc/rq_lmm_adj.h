@@ -77,10 +77,16 @@ template <typename T> __device__ __forceinline__ cptr<T> after(cptr<T> p, T dep)
 
 template <typename T> __device__ __forceinline__ T adj_exp2(T x);
 template <> __device__ __forceinline__ float adj_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
-template <> __device__ __forceinline__ double adj_exp2<double>(double x) { return exp2(x); }
+template <> __device__ __forceinline__ double adj_exp2<double>(double x) { return exp2_f64(x); }
 template <typename T> __device__ __forceinline__ T adj_rcp(T x);
 template <> __device__ __forceinline__ float adj_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ __forceinline__ double adj_rcp<double>(double x) { return 1.0 / x; }
+// 1/x for the drift factor's denominator 1 + kappa 2^-X >= 1: the Newton
+// reciprocal, or 0 beyond 2^1000 (as a division would give for an
+// overflowing denominator)
+template <> __device__ __forceinline__ double adj_rcp<double>(double x)
+{
+    return x < 0x1p1000 ? recip64(x) : 0.0;
+}
 
 // One task: the 64 paths of block `blk` of replication m (task = m n_blk + blk
 // indexes the partial rows).  GREEKS = false runs the forward pass and the

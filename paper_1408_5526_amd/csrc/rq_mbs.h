@@ -1,7 +1,8 @@
 // rq_mbs.h -- Caflisch mortgage-backed-security path, one path per lane.
 //
 // Model (MBS section), months k = 1..K, z_k = Phi^{-1}(x_{k-1}):
-//   u_k = u_{k-1} / (1 + i_{k-1})            discount factor      (FP64)
+//   u_k = u_{k-1} / (1 + i_{k-1})            discount factor      (FP64,
+//                                            Newton reciprocal)
 //   i_k = K0 exp(sigma z_k) i_{k-1}          monthly rate, K0 = exp(-sigma^2/2)
 //   w_k = K1 + K2 atan(K3 i_k + K4)          prepayment fraction
 //   PV += u_k c r_k ((1 - w_k) + w_k c_k)    cash flow m_k, discounted (FP64)
@@ -50,9 +51,14 @@ __device__ __forceinline__ void mbs_path(const MbsArgs &a, const StartEnt *__res
                                                a.g.perm + (size_t)m * a.g.perm_stride);
         }
         const T z = inv_normal(x, T(0));
+        // 1 / (1 + i) by the Newton reciprocal (within an ulp or two of the
+        // quotient): one reciprocal serves u and du; a rate beyond 2^1000
+        // (an overflowing FP32 rate included) discounts to 0, as a division
+        // would
         const double onei = 1.0 + (double)ir;
-        u = u / onei;
-        if (GRAD) du = (du - u * (double)di) / onei;
+        const double ri = onei < 0x1p1000 ? recip64(onei) : 0.0;
+        u = u * ri;
+        if (GRAD) du = (du - u * (double)di) * ri;
         const T f = K0 * fexp(sig * z);
         ir = f * ir;
         const T arg = K3 * ir + K4;
