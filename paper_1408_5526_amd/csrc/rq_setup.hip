@@ -58,40 +58,76 @@ hipError_t launch_setup(const SetupArgs &a, hipStream_t st)
 }
 
 // ---------------------------------------------------------------------------
-// sequence(): materialise x[m][i][j] (or the integers R).  A block covers a
-// tile of kTile consecutive points of one replication and all s dimensions;
-// consecutive threads write consecutive elements, so stores coalesce.
+// sequence(): materialise x[m][i][j] (or the integers R).  A block (four
+// waves) covers a tile of kTile = 64 consecutive points of one replication
+// and all s dimensions, kDimChunk dimensions at a time.  In a chunk each
+// wave takes every fourth dimension, so the dimension is wave-uniform: its
+// base and start entries arrive as scalar loads, the digit loop runs the
+// same trip count in every lane, and lane l computes point i0 + l.  The
+// chunk goes through LDS ([point][dimension]) and leaves as whole rows of
+// kDimChunk doubles per point (256 contiguous bytes), consecutive threads
+// on consecutive addresses.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 64;
+constexpr int kDimChunk = 32;
 
 template <bool PERM, bool DIGITS>
 __global__ __launch_bounds__(256) void sequence_kernel(SeqGeom g, int64_t tiles_per_m, void *out)
 {
+    __shared__ uint64_t tile[kTile][kDimChunk + 1];   // +1: the column writes fall on distinct banks
     const int64_t m = blockIdx.x / tiles_per_m;
-    const int64_t tile = blockIdx.x - m * tiles_per_m;
-    const int64_t i0 = tile * kTile;
-    const int64_t npts = (g.N - i0) < kTile ? (g.N - i0) : kTile;
+    const int64_t tl = blockIdx.x - m * tiles_per_m;
+    const int64_t i0 = tl * kTile;
+    const int npts = (int)((g.N - i0) < kTile ? (g.N - i0) : kTile);
     const int seg = (int)(i0 >> g.log2S);                 // tiles never straddle segments
     const StartEnt *st = g.starts + ((size_t)m * g.n_seg + seg) * g.s;
     const uint32_t t0 = (uint32_t)(i0 - ((int64_t)seg << g.log2S));
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const uint16_t *perm = g.perm + (size_t)m * g.perm_stride;
+    uint64_t *o = (uint64_t *)out + ((size_t)m * (size_t)g.N + (size_t)i0) * (size_t)g.s;
+    for (int j0 = 0; j0 < g.s; j0 += kDimChunk) {
+        const int nd = (g.s - j0) < kDimChunk ? (g.s - j0) : kDimChunk;
+        for (int dj = wave; dj < nd; dj += 256 / kWave) {
+            const int j = j0 + dj;
+            const PointCtx c = load_base_uniform(g.base, j);
+            const StartEnt e = load_uniform<StartEnt>(st + j);
+            uint64_t v = 0;
+            if (lane < npts) {
+                const double R = radinv_R<PERM>(c, e, t0 + (uint32_t)lane, perm);
+                v = DIGITS ? (uint64_t)R : __builtin_bit_cast(uint64_t, R / c.Pd);
+            }
+            tile[lane][dj] = v;
+        }
+        __syncthreads();
+        const int cnt = npts * nd;
+        for (int q = threadIdx.x; q < cnt; q += 256) {
+            const int r = nd == kDimChunk ? q / kDimChunk : q / nd;
+            const int cj = q - r * nd;
+            o[(size_t)r * (size_t)g.s + (size_t)(j0 + cj)] = tile[r][cj];
+        }
+        __syncthreads();
+    }
+}
+
+// Pseudo-random points (Philox4x64-10), one element per thread: the
+// counter of an element is (j/4, i, 0, 0), so consecutive elements of a row
+// come from one block of four words.
+__global__ __launch_bounds__(256) void sequence_mc_kernel(SeqGeom g, int64_t tiles_per_m, void *out)
+{
+    const int64_t m = blockIdx.x / tiles_per_m;
+    const int64_t tl = blockIdx.x - m * tiles_per_m;
+    const int64_t i0 = tl * kTile;
+    const int64_t npts = (g.N - i0) < kTile ? (g.N - i0) : kTile;
     const uint32_t nel = (uint32_t)(npts * g.s);
     const size_t obase = ((size_t)m * (size_t)g.N + (size_t)i0) * (size_t)g.s;
     for (uint32_t e = threadIdx.x; e < nel; e += blockDim.x) {
         const uint32_t ip = e / (uint32_t)g.s;
         const int j = (int)(e - ip * (uint32_t)g.s);
-        if (g.mc) {   // pseudo-random points (never with digits or permutations)
-            uint64_t c[4] = {(uint64_t)(j >> 2), (uint64_t)(i0 + ip), 0ull, 0ull};
-            philox4x64_10(c, g.seed, (uint64_t)(g.m_offset + m));
-            const int q = j & 3;
-            ((double *)out)[obase + e] = u53(q == 0 ? c[0] : q == 1 ? c[1] : q == 2 ? c[2] : c[3]);
-            continue;
-        }
-        const PointCtx c = load_base(g.base, j);
-        const double R = radinv_R<PERM>(c, st[j], t0 + ip, g.perm + (size_t)m * g.perm_stride);
-        if (DIGITS)
-            ((uint64_t *)out)[obase + e] = (uint64_t)R;
-        else
-            ((double *)out)[obase + e] = R / c.Pd;
+        uint64_t c[4] = {(uint64_t)(j >> 2), (uint64_t)(i0 + ip), 0ull, 0ull};
+        philox4x64_10(c, g.seed, (uint64_t)(g.m_offset + m));
+        const int q = j & 3;
+        ((double *)out)[obase + e] = u53(q == 0 ? c[0] : q == 1 ? c[1] : q == 2 ? c[2] : c[3]);
     }
 }
 
@@ -101,8 +137,9 @@ hipError_t launch_sequence(const SeqGeom &g, int flags, void *out, hipStream_t s
     const int64_t blocks = tiles * g.M;
     const bool perm = g.perm_on != 0;   // one shared table or one per replication
     const bool dig = (flags & kOutDigits) != 0;
-    auto k = perm ? (dig ? sequence_kernel<true, true> : sequence_kernel<true, false>)
-                  : (dig ? sequence_kernel<false, true> : sequence_kernel<false, false>);
+    auto k = g.mc ? sequence_mc_kernel
+                  : perm ? (dig ? sequence_kernel<true, true> : sequence_kernel<true, false>)
+                         : (dig ? sequence_kernel<false, true> : sequence_kernel<false, false>);
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), 0, st, g, tiles, out);
     return hipGetLastError();
 }
