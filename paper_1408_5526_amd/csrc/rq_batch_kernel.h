@@ -34,6 +34,7 @@ void batch_kernel(BatchArgs b)
 {
     constexpr int part = PHASE == 1 ? kTaskFwd : PHASE == 2 ? kTaskRev : kTaskWhole;
     __shared__ T vbar[kMaxFwd][kWave];
+    __shared__ __align__(32) T c6s[PHASE == 2 ? 1 : kMaxFwd];   // the forward passes' drift constants (not in phase 2)
     const int lane = threadIdx.x;
     const cptr<int64_t> item0 = as_const<int64_t>(b.item0);
     const cptr<BatchInst> inst = as_const<BatchInst>(b.inst);
@@ -66,13 +67,14 @@ void batch_kernel(BatchArgs b)
                 T *wt = GREEKS ? slot + lane : nullptr;
                 T *xs = GREEKS ? slot + kMaxFwd * 3 * kWave + lane : nullptr;
                 const int sel = inst[lo].n_factors * 2 + (a.g.mc ? 1 : 0);
+                T *c6p = PHASE == 2 ? nullptr : &c6s[0];
                 switch (sel) {
-                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs); break;
-                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs); break;
-                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs); break;
-                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs); break;
-                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs); break;
-                default: lmm_task<kMaxFwd, 3, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs); break;
+                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                default: lmm_task<kMaxFwd, 3, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
                 }
             } else if (PHASE != 2) {
                 const MbsArgs a = load_uniform<MbsArgs>(&b.inst[lo].mbs);

@@ -460,6 +460,33 @@ __device__ __forceinline__ cptr<T> opaque_u(cptr<T> p)
     return (cptr<T>)u;
 }
 
+// LDS tables read inside a loop: lds_base gives the table's local address
+// through an empty asm (call it inside the loop), so the reads below depend
+// on the iteration and are not hoisted into registers as loop-invariant
+// values; they stay ds_read instructions next to their use.
+template <typename T>
+using lds_ptr = const __attribute__((address_space(3))) T *;
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> lds_base(const T *table)
+{
+    uint32_t u = (uint32_t)(uintptr_t)(lds_ptr<T>)table;
+    asm volatile("" : "+v"(u));   // a vector register: the ds_read address operand
+    return (lds_ptr<T>)(uintptr_t)u;
+}
+// Entries n0..n0+3 (n0 a multiple of 4, the table aligned to 4 entries) in
+// one vector read.
+template <typename T>
+struct Quad {
+    T v[4];
+};
+template <typename T>
+__device__ __forceinline__ Quad<T> lds_quad(lds_ptr<T> table, int n0)
+{
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    const vec4 x = *(const __attribute__((address_space(3))) vec4 *)(table + n0);
+    return Quad<T>{{x[0], x[1], x[2], x[3]}};
+}
+
 __device__ __forceinline__ void acc_add(Acc &a, double x)
 {
     const double t = a.s + x;

@@ -67,11 +67,19 @@ void lmm_kernel(LmmArgs a)
     const int seg = (int)(((int64_t)blk * kBlock) >> a.g.log2S);
     const uint32_t t = (uint32_t)(i - ((int64_t)seg << a.g.log2S));
     const StartEnt *__restrict__ st = a.g.starts + ((size_t)m * a.g.n_seg + seg) * a.g.s;
-    const double *__restrict__ fwd = a.fwd;
+    const cptr<double> fwd = as_const<double>(a.fwd);   // read-only tables: scalar loads
+    const cptr<float> fwd32 = as_const<float>(a.fwd32);
     const int nf = a.n_fwd;
 
     __shared__ double red[kBlock / kWave][NFC];
     __shared__ double tot[NFC];
+    // the drift constants (log2(e) c_n in FP32, c_n in FP64), broadcast from
+    // LDS: a forward-step's first FMA then takes one scalar operand (the
+    // loading) and one vector operand (the constant), and no constant is
+    // moved to a vector register
+    __shared__ __align__(32) T c6s[NFC];
+    for (int n = tid; n < NFC; n += kBlock) c6s[n] = kF32 ? (T)fwd32[n * kRow32 + 6] : (T)fwd[n * kFwdRow + 6];
+    __syncthreads();
 
     auto r64 = [&](int n, int c) -> double { return fwd[n * kFwdRow + c]; };
 
@@ -109,10 +117,11 @@ void lmm_kernel(LmmArgs a)
             }
             w[f] = sqd * inv_normal(x, T(0));
         }
-        // One forward-step of forward n (alive in this step).
-        auto body = [&](int n) __attribute__((always_inline)) {
+        // One forward-step of forward n (alive in this step); c6 is its drift
+        // constant from LDS.
+        auto body = [&](int n, T c6) __attribute__((always_inline)) {
             if constexpr (kF32) {
-                const float *q = a.fwd32 + n * kRow32;
+                const cptr<float> q = fwd32 + n * kRow32;
                 const float g = __builtin_amdgcn_rcpf(ffma(q[7], fexp2(-X[n]), 1.0f));
 #pragma unroll
                 for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
@@ -128,7 +137,7 @@ void lmm_kernel(LmmArgs a)
                     const float r = fmaxf(ffma(e, 0.693147180559945309f, 1.0f), 0x1p-100f);
                     X[n] += __builtin_amdgcn_logf(r);
                 } else {
-                    float e = ffma(q[0], w[0], q[6]);
+                    float e = ffma(q[0], w[0], (float)c6);
 #pragma unroll
                     for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
                     X[n] += e;
@@ -146,7 +155,7 @@ void lmm_kernel(LmmArgs a)
                     for (int f = 1; f < D; ++f) e = ffma(r64(n, f), w[f], e);
                     X[n] = ffma(X[n], e, X[n]);
                 } else {
-                    double e = r64(n, 6);
+                    double e = (double)c6;
 #pragma unroll
                     for (int f = 0; f < D; ++f) e = ffma(r64(n, f), w[f], e);
                     X[n] = X[n] * exp(e);
@@ -154,12 +163,13 @@ void lmm_kernel(LmmArgs a)
             }
         };
         const unsigned alive = (unsigned)(nf - k);
+        const lds_ptr<T> c6k = lds_base(&c6s[0]);
         if constexpr (!kF32) {
             // FP64: one uniform branch per forward (its exp and division are
             // too costly to spend on dead forwards)
 #pragma unroll
             for (int n = 0; n < NFC; ++n)
-                if ((unsigned)(n - k) < alive) body(n);
+                if ((unsigned)(n - k) < alive) body(n, c6k[n]);
             continue;
         }
         // FP32: in the group holding forward k (n0 < k < n0 + kGrp) each live
@@ -170,17 +180,19 @@ void lmm_kernel(LmmArgs a)
         for (int gq = 0; gq < NFC / kGrp; ++gq) {
             const int n0 = gq * kGrp;
             if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {
+                const Quad<T> c4 = lds_quad(c6k, n0);
 #pragma unroll
                 for (int u = 0; u < kGrp; ++u)   // its live forwards only, one uniform branch each
-                    if ((unsigned)(n0 + u - k) < alive) body(n0 + u);
+                    if ((unsigned)(n0 + u - k) < alive) body(n0 + u, c4.v[u]);
             }
         }
 #pragma unroll
         for (int gq = 0; gq < NFC / kGrp; ++gq) {
             const int n0 = gq * kGrp;
             if ((unsigned)(n0 - k) < alive) {
+                const Quad<T> c4 = lds_quad(c6k, n0);
 #pragma unroll
-                for (int u = 0; u < kGrp; ++u) body(n0 + u);
+                for (int u = 0; u < kGrp; ++u) body(n0 + u, c4.v[u]);
             }
         }
     }

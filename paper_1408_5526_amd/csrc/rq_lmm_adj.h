@@ -103,7 +103,8 @@ constexpr int kTaskWhole = 0, kTaskFwd = 1, kTaskRev = 2;
 
 template <int NFC, int D, typename T, bool GREEKS, bool MC, int PART = kTaskWhole>
 __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64_t task, T *__restrict__ wt,
-                                         T (&vbar)[NFC][kWave], T *__restrict__ xs = nullptr)
+                                         T (&vbar)[NFC][kWave], T *__restrict__ xs = nullptr,
+                                         T *__restrict__ c6s = nullptr)
 {
     static_assert(NFC % 16 == 0 && NFC % kGrp == 0, "capacity must be a multiple of 16");
     constexpr bool kF32 = sizeof(T) == 4;
@@ -128,6 +129,14 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     T X[NFC], Xb[NFC];
 #pragma unroll
     for (int n = 0; n < NFC; ++n) X[n] = PART == kTaskRev ? xs[n * kWave] : T(0);
+    if constexpr (PART != kTaskRev) {
+        // the drift constants log2(e) c_n, broadcast from LDS (c6s, NFC
+        // entries): a forward-step's first FMA then takes one scalar operand
+        // (the loading) and one vector operand (the constant), and no
+        // constant is moved to a vector register
+        for (int n = lane; n < NFC; n += kWave) c6s[n] = tab[n * kAdjRow + 6];
+        __syncthreads();
+    }
 
     // ---- forward pass ----
     McPath mc;
@@ -157,20 +166,22 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             }
             w[f] = sqd * inv_normal(x, T(0));
         }
-        // one forward-step of forward n (alive in this step)
-        auto body = [&](int n) __attribute__((always_inline)) {
+        // one forward-step of forward n (alive in this step); c6 is its drift
+        // constant log2(e) c_n, read from LDS
+        auto body = [&](int n, T c6) __attribute__((always_inline)) {
             const cptr<T> q = tab + n * kAdjRow;
             const T g = G(X[n], q[7]);
 #pragma unroll
             for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
             // the (small) increment log2(e) (c_n + a_n . w) is formed first and
             // added to the O(1) state once
-            T e = ffma(q[0], w[0], q[6]);
+            T e = ffma(q[0], w[0], c6);
 #pragma unroll
             for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
             X[n] += e;
         };
         const unsigned alive = (unsigned)(nf - k);
+        const lds_ptr<T> c6k = lds_base(c6s);
         if constexpr (kF32) {
             // groups of kGrp forwards: in the one holding forward k (n0 < k <
             // n0 + kGrp) each live forward runs behind its own uniform branch,
@@ -180,23 +191,25 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             for (int gq = 0; gq < NFC / kGrp; ++gq) {
                 const int n0 = gq * kGrp;
                 if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {
+                    const Quad<T> c4 = lds_quad(c6k, n0);
 #pragma unroll
                     for (int u = 0; u < kGrp; ++u)   // its live forwards only, one uniform branch each
-                        if ((unsigned)(n0 + u - k) < alive) body(n0 + u);
+                        if ((unsigned)(n0 + u - k) < alive) body(n0 + u, c4.v[u]);
                 }
             }
 #pragma unroll
             for (int gq = 0; gq < NFC / kGrp; ++gq) {
                 const int n0 = gq * kGrp;
                 if ((unsigned)(n0 - k) < alive) {
+                    const Quad<T> c4 = lds_quad(c6k, n0);
 #pragma unroll
-                    for (int u = 0; u < kGrp; ++u) body(n0 + u);
+                    for (int u = 0; u < kGrp; ++u) body(n0 + u, c4.v[u]);
                 }
             }
         } else {
 #pragma unroll
             for (int n = 0; n < NFC; ++n)
-                if ((unsigned)(n - k) < alive) body(n);
+                if ((unsigned)(n - k) < alive) body(n, c6k[n]);
         }
         if constexpr (GREEKS) {
 #pragma unroll
@@ -467,13 +480,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T)
 void lmm_adj_fwd_kernel(LmmArgs a)
 {
     __shared__ T vbar[NFC][kWave];   // not touched by the forward half
+    __shared__ __align__(32) T c6s[NFC];
     const int64_t local = blockIdx.x;
     const int64_t task = a.task0 + local;
     const int m = (int)(task / a.n_blk);
     const int blk = (int)(task - (int64_t)m * a.n_blk);
     T *wt = (T *)a.wtop + local * ((int64_t)a.n_fwd * D * kWave) + threadIdx.x;
     T *xs = (T *)a.xs + local * ((int64_t)NFC * kWave) + threadIdx.x;
-    lmm_task<NFC, D, T, true, MC, kTaskFwd>(a, m, blk, task, wt, vbar, xs);
+    lmm_task<NFC, D, T, true, MC, kTaskFwd>(a, m, blk, task, wt, vbar, xs, c6s);
 }
 
 // FP32: the compiler is asked for two waves per SIMD (at most 256 registers);
