@@ -162,7 +162,7 @@ def cpu_baseline(model, N: int, seed: int, m_per_core: int):
     cores = O.num_threads()
     m_sub = m_per_core * cores
     t0 = time.perf_counter()
-    O.price_caplets(model, N, m_sub, seed)
+    cpu_baseline.theta = O.price_caplets(model, N, m_sub, seed)   # kept for the error statement
     dt = time.perf_counter() - t0
     # the same oracle on one core (2 replications)
     O.set_num_threads(1)
@@ -402,6 +402,7 @@ def main(argv=None):
     head = args.precision
     ms, kms, res = _time_steps(step(head), args.steps, args.warmup)
     out_extra = {}
+    res64 = None
     if not args.skip_fp64 and head != "fp64":
         ms64, kms64, res64 = _time_steps(step("fp64"), args.steps, args.warmup)
         rq64, se64 = res64.mean[-1].item(), res64.se[-1].item()
@@ -514,6 +515,19 @@ def main(argv=None):
         line["small_call"] = small_call_leg(rq, I, torch, dev)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(model, N, seed, args.cpu_m_per_core)
+        # every GPU form's estimates against the FP64 oracle on the replications
+        # the oracle computed (all 81 outputs: 80 caplets and the book)
+        import numpy as np
+        th_o = cpu_baseline.theta
+        errs = {}
+        for name, r in (("fp32_greeks", res_g), ("fp32", res), ("fp64", res64)):
+            if r is None:
+                continue
+            th = r.theta[:th_o.shape[0]].cpu().numpy()
+            rel = np.abs(th - th_o) / np.abs(th_o)
+            errs[name] = {"max_rel": float(rel.max()), "book_max_rel": float(rel[:, -1].max())}
+        line["error_vs_oracle"] = {"replications": int(th_o.shape[0]), "outputs": int(th_o.shape[1]),
+                                   "theta_rel_err": errs}
         if args.generators:
             line["generators"]["cpu_recursive"] = cpu_generator_baseline()
             line["generators"]["cpu_recursive_simd"] = cpu_simd_generator()
