@@ -419,12 +419,17 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                 const int n0 = gq * kGrp;
                 if ((unsigned)(k - n0 - 1) < (unsigned)(kGrp - 1)) {        // n0 < k < n0 + kGrp
                     // the group's rows, all requested before the first is used
-                    // (one scalar-load wait for the group, not one per forward)
+                    // (one scalar-load wait for the group, not one per forward).
+                    // Forward n0 < k is dead and skipped; forward n0 + kGrp - 1 >= k
+                    // is live, or beyond the model, where its zero row makes the
+                    // forward-step a no-op, so it runs unmasked; the ones between
+                    // are masked (branches here cost SGPRs the loop needs).
                     T qg[kGrp][kAdjRow];
 #pragma unroll
-                    for (int u = 0; u < kGrp; ++u) load_row(qg[u], tab + (n0 + u) * kAdjRow);
+                    for (int u = 1; u < kGrp; ++u) load_row(qg[u], tab + (n0 + u) * kAdjRow);
+                    body(n0 + kGrp - 1, qg[kGrp - 1], vbar[n0 + kGrp - 1][lane], T(1), std::false_type{}, none);
 #pragma unroll
-                    for (int u = kGrp - 1; u >= 0; --u)   // masked (branches here cost SGPRs the loop needs)
+                    for (int u = kGrp - 2; u >= 1; --u)
                         body(n0 + u, qg[u], vbar[n0 + u][lane],
                              __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                                  (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
