@@ -33,8 +33,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
 void batch_kernel(BatchArgs b)
 {
     constexpr int part = PHASE == 1 ? kTaskFwd : PHASE == 2 ? kTaskRev : kTaskWhole;
-    __shared__ T vbar[kMaxFwd][kWave];
-    __shared__ __align__(32) T c6s[PHASE == 2 ? 1 : kMaxFwd];   // the forward passes' drift constants (not in phase 2)
+    // vega rows (phase 2 in FP32 keeps VR of them in registers) and the drift
+    // constants (every phase but FP64's phase 2, whose vega rows take the LDS)
+    constexpr int VR = PHASE == 2 ? rev_reg_rows<kMaxFwd, T>() : 0;
+    constexpr bool kC6 = !(PHASE == 2 && sizeof(T) == 8);
+    __shared__ T vbar[kMaxFwd - VR][kWave];
+    __shared__ __align__(32) T c6s[kC6 ? kMaxFwd : 1];
     const int lane = threadIdx.x;
     const cptr<int64_t> item0 = as_const<int64_t>(b.item0);
     const cptr<BatchInst> inst = as_const<BatchInst>(b.inst);
@@ -67,14 +71,14 @@ void batch_kernel(BatchArgs b)
                 T *wt = GREEKS ? slot + lane : nullptr;
                 T *xs = GREEKS ? slot + kMaxFwd * 3 * kWave + lane : nullptr;
                 const int sel = inst[lo].n_factors * 2 + (a.g.mc ? 1 : 0);
-                T *c6p = PHASE == 2 ? nullptr : &c6s[0];
+                T *c6p = kC6 ? &c6s[0] : nullptr;
                 switch (sel) {
-                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                default: lmm_task<kMaxFwd, 3, T, GREEKS, false, part>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                default: lmm_task<kMaxFwd, 3, T, GREEKS, false, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
                 }
             } else if (PHASE != 2) {
                 const MbsArgs a = load_uniform<MbsArgs>(&b.inst[lo].mbs);

@@ -98,15 +98,32 @@ template <> __device__ __forceinline__ double adj_rcp<double>(double x)
 // of its two halves for the two-kernel form: kTaskFwd runs the forward pass
 // and stores the final states at xs ([n][lane], n < NFC); kTaskRev loads them
 // and runs the payoffs and the reverse sweep.  The halves do exactly the
-// arithmetic of the whole task.
+// arithmetic of the whole task.  c6s is the block's LDS table of the NFC
+// drift constants log2(e) c_n, filled by the task; the forward pass always
+// uses it, the FP32 reverse sweep too (FP64 passes none to its reverse half).
+// The vega rows of forwards n >= NFC - VR are held in registers, the others
+// in vbar (NFC - VR rows).
 constexpr int kTaskWhole = 0, kTaskFwd = 1, kTaskRev = 2;
 
-template <int NFC, int D, typename T, bool GREEKS, bool MC, int PART = kTaskWhole>
+// LDS of one 64-lane wave at two waves per SIMD: the CU's 160 KB over 8
+constexpr int kLdsPerWave2 = 160 * 1024 / 8;
+// Vega rows an FP32 reverse half holds in registers so that its NFC vega
+// rows and its NFC drift constants fit kLdsPerWave2 (two at NFC = 80; the
+// registers are there, as the sweep's state takes about 190 of 256)
+template <int NFC, typename T>
+constexpr int rev_reg_rows()
+{
+    constexpr int over = (NFC * kWave + NFC) * (int)sizeof(T) - kLdsPerWave2;
+    return sizeof(T) == 4 && over > 0 ? (over + kWave * (int)sizeof(T) - 1) / (kWave * (int)sizeof(T)) : 0;
+}
+
+template <int NFC, int D, typename T, bool GREEKS, bool MC, int PART = kTaskWhole, int VR = 0>
 __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64_t task, T *__restrict__ wt,
-                                         T (&vbar)[NFC][kWave], T *__restrict__ xs = nullptr,
+                                         T (*__restrict__ vbar)[kWave], T *__restrict__ xs = nullptr,
                                          T *__restrict__ c6s = nullptr)
 {
     static_assert(NFC % 16 == 0 && NFC % kGrp == 0, "capacity must be a multiple of 16");
+    static_assert(VR >= 0 && VR < kGrp, "at most kGrp - 1 vega rows in registers");
     constexpr bool kF32 = sizeof(T) == 4;
     constexpr T kLn2 = T(0.69314718055994530942);
     const int lane = threadIdx.x;
@@ -127,6 +144,15 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     const StartEnt *__restrict__ st = a.g.starts + ((size_t)m * a.g.n_seg + seg) * a.g.s;
 
     T X[NFC], Xb[NFC];
+    // vega row n: vbar[n][lane], or a register for n >= kLdsRows (n is a
+    // compile-time constant at every use, in unrolled loops)
+    constexpr int kLdsRows = NFC - VR;
+    T vr[VR > 0 ? VR : 1] = {};
+    auto vget = [&](int n) -> T { return n >= kLdsRows ? vr[n - kLdsRows] : vbar[n][lane]; };
+    auto vset = [&](int n, T v) {
+        if (n >= kLdsRows) vr[n - kLdsRows] = v;
+        else vbar[n][lane] = v;
+    };
 #pragma unroll
     for (int n = 0; n < NFC; ++n) X[n] = PART == kTaskRev ? xs[n * kWave] : T(0);
     if constexpr (PART != kTaskRev) {
@@ -287,7 +313,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                         // delta / (1 + delta L_n) = rn num_{n-1}: no second division
                         double dL = -(rn * num_prev) * (book - before);
                         if (ex > 0.0) dL += flag * rn;
-                        vbar[n][lane] = (T)(dL * Lf * 0.69314718055994530942);
+                        vset(n, (T)(dL * Lf * 0.69314718055994530942));
                         before += Pn;
                     } else {
                         book += Pn;
@@ -315,8 +341,12 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     // ---- reverse sweep ----
 #pragma unroll
     for (int n = 0; n < NFC; ++n) {   // rows beyond n_fwd hold 0
-        Xb[n] = vbar[n][lane];
-        vbar[n][lane] = T(0);
+        Xb[n] = vget(n);
+        vset(n, T(0));
+    }
+    if constexpr (kF32 && PART == kTaskRev) {   // the drift constants, as the forward half has them
+        for (int n = lane; n < NFC; n += kWave) c6s[n] = tab[n * kAdjRow + 6];
+        __syncthreads();
     }
     T wn[D];
 #pragma unroll
@@ -334,25 +364,29 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             for (int f = 0; f < D; ++f) wn[f] = wt[(size_t)((k - 1) * D + f) * kWave];
         }
         // adjoint of one forward-step, w = w_n on entry, w_{n-1} on exit;
-        // on = 0 leaves everything unchanged.  q is the forward's table row
-        // and vb its (sigma-scaled) vega entry so far.  pre() runs right
+        // on = 0 leaves everything unchanged.  q is the forward's table row,
+        // vb its (sigma-scaled) vega entry so far and c6 its drift constant
+        // log2(e) c_n (in FP32 a vector operand read from LDS, so that the
+        // increment's first FMA takes it beside the row's scalar loading).  pre() runs right
         // after the row's first use, once the wave has waited for the row: it
         // issues the next forward's row and vega loads and stores the previous
         // forward-step's vega entry, so that the one wait per forward-step
         // finds all three long done.
         T pend = T(0);   // the previous unmasked forward-step's new vega entry, not yet stored
         const int nfk = opaque_u(nf);   // tests on it stay inside the step loop
-        auto body = [&](int n, const auto &q, T vb, T on, auto masked, auto pre) __attribute__((always_inline)) {
+        auto body = [&](int n, const auto &q, T vb, T c6, T on, auto masked, auto pre) __attribute__((always_inline)) {
             constexpr bool MASKED = decltype(masked)::value;
-            T P = q[0] * w[0];                        // log2(e) a_n . w_n
+            // the increment e = log2(e) (c_n + a_n . w_n), formed as the
+            // forward pass forms it
+            T e = ffma(q[0], w[0], c6);
 #pragma unroll
-            for (int f = 1; f < D; ++f) P = ffma(q[f], w[f], P);
+            for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
             if constexpr (!std::is_same<decltype(pre), NoPre>::value) {
                 __builtin_amdgcn_sched_barrier(0);
                 pre();
                 __builtin_amdgcn_sched_barrier(0);
             }
-            const T y = MASKED ? ffma(-(P + q[6]), on, X[n]) : X[n] - (P + q[6]);
+            const T y = MASKED ? ffma(-e, on, X[n]) : X[n] - e;
             X[n] = y;
             const T g = G(y, q[7]);
             const T ge = MASKED ? g * on : g;
@@ -363,9 +397,9 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 #pragma unroll
             for (int f = 1; f < D; ++f) da = ffma(q[3 + f], Wb[f], da);
             const T h = ge * da;
-            const T vnew = vb + ffma(xb, ffma(T(2), q[6], P), h);
+            const T vnew = vb + ffma(xb, e + q[6], h);   // P + 2 log2(e) c_n = e + log2(e) c_n
             if constexpr (MASKED || std::is_same<decltype(pre), NoPre>::value)
-                vbar[n][lane] = vnew;
+                vset(n, vnew);
             else
                 pend = vnew;   // written by the next forward-step, after its wait
             Xb[n] = ffma(kLn2, ffma(-g, h, h), Xb[n]);
@@ -377,17 +411,19 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         if constexpr (kF32) {
             // wholly alive groups first (unmasked), the group holding forward k
             // last (masked), as in the forward pass but in reverse order.  The
-            // live groups' rows and vega entries are software-pipelined: rr and
-            // vo hold the next forward's.
+            // live groups' rows, vega entries and drift constants are
+            // software-pipelined: rr, vo and co hold the next forward's.
+            const lds_ptr<T> c6k = lds_base(c6s);
             T rr[kAdjRow] = {};
-            T vo = T(0);
+            T vo = T(0), co = T(0);
 #pragma unroll
             for (int gq = NFC / kGrp - 1; gq >= 0; --gq) {
                 const int n0 = gq * kGrp;
                 if ((unsigned)(n0 - k) < alive) {                           // k <= n0 < n_fwd
                     if (n0 + kGrp >= nfk) {                                 // highest live group
                         load_row(rr, tab + (n0 + kGrp - 1) * kAdjRow);
-                        vo = vbar[n0 + kGrp - 1][lane];
+                        vo = vget(n0 + kGrp - 1);
+                        co = c6k[n0 + kGrp - 1];
                     }
 #pragma unroll
                     for (int u = kGrp - 1; u >= 0; --u) {
@@ -395,22 +431,24 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                         T q[kAdjRow];
 #pragma unroll
                         for (int e = 0; e < kAdjRow; ++e) q[e] = rr[e];
-                        const T vb = vo;
-                        body(n, q, vb, T(1), std::false_type{}, [&] {
+                        const T vb = vo, c6 = co;
+                        body(n, q, vb, c6, T(1), std::false_type{}, [&] {
                             const cptr<T> t2 = after(tab, q[0]);
                             __builtin_amdgcn_sched_barrier(0);
                             if (n > 0) {
                                 load_row(rr, t2 + (n - 1) * kAdjRow);
-                                vo = vbar[n - 1][lane];
+                                vo = vget(n - 1);
+                                co = c6k[n - 1];
                             }
                             // the previous forward-step (n + 1) ran unless this is
                             // the highest live group's first
-                            if (n + 1 < NFC && (u < kGrp - 1 || n0 + kGrp < nfk)) vbar[n + 1][lane] = pend;
+                            if (n + 1 < NFC && (u < kGrp - 1 || n0 + kGrp < nfk)) vset(n + 1, pend);
                         });
                     }
                 }
             }
-            {   // the last unmasked forward-step's entry: forward n = k rounded up to kGrp
+            {   // the last unmasked forward-step's entry: forward n = k rounded up to
+                // kGrp, below NFC and so (VR < kGrp) an LDS row
                 const int nl = (k + kGrp - 1) & ~(kGrp - 1);
                 if (nl < nf) vbar[nl][lane] = pend;
             }
@@ -427,10 +465,12 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     T qg[kGrp][kAdjRow];
 #pragma unroll
                     for (int u = 1; u < kGrp; ++u) load_row(qg[u], tab + (n0 + u) * kAdjRow);
-                    body(n0 + kGrp - 1, qg[kGrp - 1], vbar[n0 + kGrp - 1][lane], T(1), std::false_type{}, none);
+                    const Quad<T> c4 = lds_quad(c6k, n0);
+                    body(n0 + kGrp - 1, qg[kGrp - 1], vget(n0 + kGrp - 1), c4.v[kGrp - 1], T(1), std::false_type{},
+                         none);
 #pragma unroll
                     for (int u = kGrp - 2; u >= 1; --u)
-                        body(n0 + u, qg[u], vbar[n0 + u][lane],
+                        body(n0 + u, qg[u], vget(n0 + u), c4.v[u],
                              __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
                                  (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
                              std::true_type{}, none);
@@ -439,8 +479,10 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         } else {
 #pragma unroll
             for (int n = NFC - 1; n >= 0; --n)
-                if ((unsigned)(n - k) < alive)
-                    body(n, tab + n * kAdjRow, vbar[n][lane], T(1), std::false_type{}, none);
+                if ((unsigned)(n - k) < alive) {
+                    const cptr<T> q = tab + n * kAdjRow;
+                    body(n, q, vget(n), q[6], T(1), std::false_type{}, none);
+                }
         }
     }
 
@@ -464,7 +506,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             if (wr) gout[o] = s;
 #pragma unroll
             for (int q = 0; q < 16; ++q)   // sigma_n vega_n / sigma_n
-                V[q] = (double)vbar[c * 16 + q][lane] * f3[(c * 16 + q) * kFwdRow + 11] * act;
+                V[q] = (double)vget(c * 16 + q) * f3[(c * 16 + q) * kFwdRow + 11] * act;
             s = wave_sum16(V, lane);
             if (wr) gout[nf + 1 + o] = s;
         }
@@ -501,14 +543,20 @@ template <int NFC, int D, typename T, bool MC>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
 void lmm_adj_rev_kernel(LmmArgs a)
 {
-    __shared__ T vbar[NFC][kWave];
+    constexpr int VR = rev_reg_rows<NFC, T>();
+    __shared__ T vbar[NFC - VR][kWave];
     const int64_t local = blockIdx.x;
     const int64_t task = a.task0 + local;
     const int m = (int)(task / a.n_blk);
     const int blk = (int)(task - (int64_t)m * a.n_blk);
     T *wt = (T *)a.wtop + local * ((int64_t)a.n_fwd * D * kWave) + threadIdx.x;
     T *xs = (T *)a.xs + local * ((int64_t)NFC * kWave) + threadIdx.x;
-    lmm_task<NFC, D, T, true, MC, kTaskRev>(a, m, blk, task, wt, vbar, xs);
+    if constexpr (sizeof(T) == 4) {
+        __shared__ __align__(32) T c6s[NFC];
+        lmm_task<NFC, D, T, true, MC, kTaskRev, VR>(a, m, blk, task, wt, vbar, xs, c6s);
+    } else {   // FP64: the vega rows take the LDS of one wave per SIMD
+        lmm_task<NFC, D, T, true, MC, kTaskRev>(a, m, blk, task, wt, vbar, xs);
+    }
 }
 
 // One half (part kTaskFwd or kTaskRev) over tasks [a.task0, a.task0 +
