@@ -284,7 +284,8 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     const double onep = 1.0 + delta * Lf;
                     num *= onep;
                     const double ex = Lf - f1[n * kFwdRow + 8];
-                    B = __builtin_fma(B, onep, ex > 0.0 ? f1[n * kFwdRow + 9] * (delta * ex) : 0.0);
+                    const double pay = f1[n * kFwdRow + 9] * (delta * ex);   // a select, not a branch
+                    B = __builtin_fma(B, onep, ex > 0.0 ? pay : 0.0);
                 }
             }
         }
@@ -318,8 +319,11 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     } else {
                         book += Pn;
                     }
-                    if (pp) pp[n < nf ? n : nf] = Pn;   // beyond n_fwd: 0 into the book slot, rewritten below
                     V[q] = Pn * act;
+                }
+                if (pp) {   // (an active lane: V = Pn) beyond n_fwd: 0 into the book slot, rewritten below
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) pp[c * 16 + q < nf ? c * 16 + q : nf] = V[q];
                 }
                 const double sv = wave_sum16(V, lane);
                 const int o = c * 16 + (lane >> 2);
