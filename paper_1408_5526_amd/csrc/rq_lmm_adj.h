@@ -283,13 +283,16 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     const double Lf = f1[n * kFwdRow + 7] * (double)adj_exp2<T>(X[n]);
                     const double onep = 1.0 + delta * Lf;
                     num *= onep;
-                    const double ex = Lf - f1[n * kFwdRow + 8];
-                    const double pay = f1[n * kFwdRow + 9] * (delta * ex);   // a select, not a branch
-                    B = __builtin_fma(B, onep, ex > 0.0 ? pay : 0.0);
+                    const double ex = __builtin_fmax(Lf - f1[n * kFwdRow + 8], 0.0);   // (L_n - K_n)^+
+                    B = __builtin_fma(B, onep, f1[n * kFwdRow + 9] * (delta * ex));
                 }
             }
         }
         book = B / num;
+    }
+    if constexpr (GREEKS) {   // pass 2 forms 2^X again: keep pass 1's values from living on in registers
+#pragma unroll
+        for (int n = 0; n < NFC; ++n) asm volatile("" : "+v"(X[n]));
     }
     {
         const cptr<double> f2 = opaque_u(fwd);
