@@ -42,15 +42,15 @@ if ROOT not in sys.path:
 #  * payoff (80, pricing kernel): 2^X and the fixing value (2), 1 + delta L
 #    (2), L - K (1), numeraire product (1), Newton reciprocal (rcp and 4
 #    FMA: 9), delta (L - K) / num times the caplet flag (3), the book (1): 19;
-#  * reverse forward-step (3,240, adjoint): P = log2(e) a.w (mul, 2 FMA: 5),
-#    the pre-step state X - (P + c) (2), the drift factor (4), Wbar +=
-#    Xbar log2(e) a (3 FMA: 6), delta a.Wbar (mul, 2 FMA: 5), h = g (delta
-#    a.Wbar) (1), the vega entry (2 FMA, add: 5), Xbar += ln2 h (1 - g)
-#    (2 FMA: 4), the w rewind (3 FMA: 6): 38;
+#  * reverse forward-step (3,240, adjoint): the increment e = log2(e)(c +
+#    a.w) (3 FMA: 6), the pre-step state X - e (1), the drift factor (4),
+#    Wbar += Xbar log2(e) a (3 FMA: 6), delta a.Wbar (mul, 2 FMA: 5), h = g
+#    (delta a.Wbar) (1), the vega entry (e + c, FMA, add: 4), Xbar += ln2 h
+#    (1 - g) (2 FMA: 4), the w rewind (3 FMA: 6): 37;
 #  * payoff section of the reverse kernel (80): the book over a common
 #    denominator (10), the payoffs again with their adjoint (27), the delta
 #    and vega outputs (4): 41.
-FLOPS_FWD_STEP, FLOPS_COORD, FLOPS_PAYOFF, FLOPS_REV_STEP, FLOPS_PAYOFF_ADJ = 17, 28, 19, 38, 41
+FLOPS_FWD_STEP, FLOPS_COORD, FLOPS_PAYOFF, FLOPS_REV_STEP, FLOPS_PAYOFF_ADJ = 17, 28, 19, 37, 41
 N_FS, N_COORD, N_FWD = 3_240, 240, 80
 FLOPS_PER_PATH_LMM80 = N_FS * FLOPS_FWD_STEP + N_COORD * FLOPS_COORD + N_FWD * FLOPS_PAYOFF
 # The adjoint's two kernels: the forward passes (no payoffs), then the
