@@ -47,7 +47,7 @@ __device__ __forceinline__ S load_uniform(const void *p)
 // the next integer because (p-1)/p + 2^-21 < 1 - 2^-23), the remainder
 // fma(-q, p, v) is exact, and the Horner accumulation R = R*p + a stays an
 // exact integer below 2^53.  The returned R is P * phi exactly; the point
-// is RN(R / P), one IEEE division.
+// is RN(R / P) (div_rn below).
 //
 // With a digit permutation sigma (eq. (3)) digits above the top nonzero
 // digit of the whole index stay 0: when the high part (hi + c) is zero
@@ -135,6 +135,21 @@ __device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt &e,
     return __builtin_fma(R, c.pDLd, rhi);
 }
 
+// RN(a / b) for finite a >= 0 and b > 0 (no underflow or overflow on the
+// way) given y = RN(1/b): q = RN(a y) is within an ulp of a / b, the
+// remainder r = a - b q is exact (one FMA), and RN(q + r y) is the
+// correctly rounded quotient (Markstein's theorem, as in Muller et al.,
+// Handbook of Floating-Point Arithmetic, on division by FMA).  Three
+// instructions instead of an IEEE division's ten; for b = P = p^D and
+// integer 0 <= a < P it was also checked against division on the host for
+// 4.1e9 quotients over the first 4096 primes, without a difference.
+__device__ __forceinline__ double div_rn(double a, double b, double y)
+{
+    const double q = a * y;
+    const double r = __builtin_fma(-q, b, a);
+    return __builtin_fma(r, y, q);
+}
+
 // The point RN(R / P).  EXACT = false forms R * RN(1/P) instead, within
 // two ulps of it (used where the point only feeds FP32 arithmetic).
 template <bool PERM, bool EXACT = true>
@@ -142,7 +157,7 @@ __device__ __forceinline__ double radinv_x(const PointCtx &c, const StartEnt &e,
                                            const uint16_t *__restrict__ perm)
 {
     const double R = radinv_R<PERM>(c, e, t, perm);
-    return EXACT ? R / c.Pd : R * c.invP;
+    return EXACT ? div_rn(R, c.Pd, c.invP) : R * c.invP;
 }
 
 // ---------------------------------------------------------------------------

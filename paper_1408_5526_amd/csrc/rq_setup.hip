@@ -64,9 +64,12 @@ hipError_t launch_setup(const SetupArgs &a, hipStream_t st)
 // wave takes every fourth dimension, so the dimension is wave-uniform: its
 // base and start entries arrive as scalar loads, the digit loop runs the
 // same trip count in every lane, and lane l computes point i0 + l.  The
-// chunk goes through LDS ([point][dimension]) and leaves as whole rows of
-// kDimChunk doubles per point (256 contiguous bytes), consecutive threads
-// on consecutive addresses.
+// chunk goes through LDS ([point][dimension]; one buffer, which keeps eight
+// blocks per CU: two buffers and one barrier per chunk instead of two ran
+// 35% slower at four) and leaves as whole rows of
+// kDimChunk values per point (256 contiguous bytes): 16 bytes per thread
+// for a whole chunk of a whole tile when s is even and the output 16-byte
+// aligned (then so is every row), else 8 bytes per thread.
 // ---------------------------------------------------------------------------
 constexpr int kTile = 64;
 constexpr int kDimChunk = 32;
@@ -83,9 +86,12 @@ __global__ __launch_bounds__(256) void sequence_kernel(SeqGeom g, int64_t tiles_
     const StartEnt *st = g.starts + ((size_t)m * g.n_seg + seg) * g.s;
     const uint32_t t0 = (uint32_t)(i0 - ((int64_t)seg << g.log2S));
     const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
+    // uniform over the wave: the dimension loop's entries then come by scalar
+    // loads and its digit loop runs on scalar trip counts
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const uint16_t *perm = g.perm + (size_t)m * g.perm_stride;
     uint64_t *o = (uint64_t *)out + ((size_t)m * (size_t)g.N + (size_t)i0) * (size_t)g.s;
+    const bool wide = npts == kTile && (g.s & 1) == 0 && ((uintptr_t)out & 15) == 0;
     for (int j0 = 0; j0 < g.s; j0 += kDimChunk) {
         const int nd = (g.s - j0) < kDimChunk ? (g.s - j0) : kDimChunk;
         for (int dj = wave; dj < nd; dj += 256 / kWave) {
@@ -95,16 +101,29 @@ __global__ __launch_bounds__(256) void sequence_kernel(SeqGeom g, int64_t tiles_
             uint64_t v = 0;
             if (lane < npts) {
                 const double R = radinv_R<PERM>(c, e, t0 + (uint32_t)lane, perm);
-                v = DIGITS ? (uint64_t)R : __builtin_bit_cast(uint64_t, R / c.Pd);
+                v = DIGITS ? (uint64_t)R : __builtin_bit_cast(uint64_t, div_rn(R, c.Pd, c.invP));
             }
             tile[lane][dj] = v;
         }
         __syncthreads();
-        const int cnt = npts * nd;
-        for (int q = threadIdx.x; q < cnt; q += 256) {
-            const int r = nd == kDimChunk ? q / kDimChunk : q / nd;
-            const int cj = q - r * nd;
-            o[(size_t)r * (size_t)g.s + (size_t)(j0 + cj)] = tile[r][cj];
+        if (wide && nd == kDimChunk) {
+            // 16 threads per row, two dimensions each; 16 rows per pass
+            const int c2 = (threadIdx.x & 15) * 2;
+            int r = threadIdx.x >> 4;
+            uint64_t *dst = o + (size_t)r * (size_t)g.s + (size_t)(j0 + c2);
+            const size_t step = (size_t)16 * (size_t)g.s;
+            for (; r < kTile; r += 16, dst += step) {
+                typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+                const u64x2 v = {tile[r][c2], tile[r][c2 + 1]};
+                *(u64x2 *)dst = v;
+            }
+        } else {
+            const int cnt = npts * nd;
+            for (int q = threadIdx.x; q < cnt; q += 256) {
+                const int r = q / nd;
+                const int cj = q - r * nd;
+                o[(size_t)r * (size_t)g.s + (size_t)(j0 + cj)] = tile[r][cj];
+            }
         }
         __syncthreads();
     }
