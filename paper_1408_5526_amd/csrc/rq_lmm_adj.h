@@ -467,20 +467,27 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     // (one scalar-load wait for the group, not one per forward).
                     // Forward n0 < k is dead and skipped; forward n0 + kGrp - 1 >= k
                     // is live, or beyond the model, where its zero row makes the
-                    // forward-step a no-op, so it runs unmasked; the ones between
-                    // are masked (branches here cost SGPRs the loop needs).
+                    // forward-step a no-op, so it runs unmasked.  One uniform
+                    // branch skips the ones between when k = n0 + kGrp - 1; inside
+                    // it forward n0 + kGrp - 2 is live (or beyond the model) and
+                    // runs unmasked, the rest are masked (a branch per forward
+                    // costs SGPRs the loop needs).
                     T qg[kGrp][kAdjRow];
 #pragma unroll
                     for (int u = 1; u < kGrp; ++u) load_row(qg[u], tab + (n0 + u) * kAdjRow);
                     const Quad<T> c4 = lds_quad(c6k, n0);
                     body(n0 + kGrp - 1, qg[kGrp - 1], vget(n0 + kGrp - 1), c4.v[kGrp - 1], T(1), std::false_type{},
                          none);
+                    if (k <= n0 + kGrp - 2) {
+                        body(n0 + kGrp - 2, qg[kGrp - 2], vget(n0 + kGrp - 2), c4.v[kGrp - 2], T(1),
+                             std::false_type{}, none);
 #pragma unroll
-                    for (int u = kGrp - 2; u >= 1; --u)
-                        body(n0 + u, qg[u], vget(n0 + u), c4.v[u],
-                             __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
-                                 (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
-                             std::true_type{}, none);
+                        for (int u = kGrp - 3; u >= 1; --u)
+                            body(n0 + u, qg[u], vget(n0 + u), c4.v[u],
+                                 __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(
+                                     (unsigned)(n0 + u - k) < alive ? 0x3f800000u : 0u)),
+                                 std::true_type{}, none);
+                    }
                 }
             }
         } else {
