@@ -202,3 +202,24 @@ def test_autograd_functions():
     pv = rq.MBSPrice.apply(i0, I.mbs_paper(60), 512, 2, 5, "fp64")
     pv.backward()
     assert i0.grad.item() == float(_np(rq.MBSPrice.last.greeks.mean)[0])
+
+
+def test_mbs_tangent_full_size_sampled_replications():
+    # the Greeks workload's MBS pool (360 months, N = 2^16, M = 256, the
+    # launch the benchmark's Greeks configuration makes): dPV/di0 of three
+    # sampled replications against the oracle's central difference of each
+    # replication alone (m_offset), in both precisions
+    from dataclasses import replace
+    c = [x for x in I.cfg4() if x.kind == "mbs"][0]
+    p, N, M, seed = c.model, c.N, c.M, c.seed
+    _say("mbs tangent full size", N, M)
+    g64 = _np(rq.price_mbs(p, N, M, seed, precision="fp64", greeks=True).greeks.theta)
+    g32 = _np(rq.price_mbs(p, N, M, seed, precision="fp32", greeks=True).greeks.theta)
+    h = 1e-4 * p.i0
+    for m in (0, 131, 255):
+        up = O.price_mbs(replace(p, i0=p.i0 + h), N, 1, seed, m_offset=m)[0, 0]
+        dn = O.price_mbs(replace(p, i0=p.i0 - h), N, 1, seed, m_offset=m)[0, 0]
+        fd = (up - dn) / (2 * h)
+        _say("mbs full size", m, "fd", fd, "fp64", g64[m, 0], "fp32", g32[m, 0])
+        assert abs(g64[m, 0] - fd) <= 1e-6 * abs(fd)
+        assert abs(g32[m, 0] - fd) <= 1e-4 * abs(fd)

@@ -106,3 +106,43 @@ def test_adjoint_greeks_match_black_within_se_plus_bias(name, mk, N, M, seed, pr
     bound = 3.0 * np.sqrt(se ** 2 + se_b ** 2) + tol
     _say("black worst dev/bound", float((dev / bound).max()))
     assert (dev <= bound).all(), (dev / bound)
+
+
+def test_adjoint_full_size_sampled_replications_match_oracle_fd():
+    # The benchmark's launch: the 80-forward, 3-factor book with Greeks at
+    # N = 2^16, M = 1024 (FP32: six chunks of tasks; FP64: eleven).  On two
+    # sampled replications, seven sampled Greeks (deltas of forwards 1, 40
+    # and 80, the spot delta, vegas of forwards 1, 40 and 80) against the
+    # oracle's central differences of that replication alone (m_offset), the
+    # bumped pricings run side by side (the oracle releases the GIL).  ATM
+    # strikes: the kink-aware bump and bar of the at-the-money tests above.
+    from concurrent.futures import ThreadPoolExecutor
+    c = I.cfg3()
+    model, N, M, seed = c.model, c.N, c.M, c.seed
+    nf = model.n_fwd
+    _say("adjoint full size", N, M)
+    g32 = _np(rq.price_caplets(model, N, M, seed, precision="fp32", greeks=True).greeks.theta)
+    g64 = _np(rq.price_caplets(model, N, M, seed, precision="fp64", greeks=True).greeks.theta)
+    cols = {"dL1": (0, "L0", 1), "dL40": (39, "L0", 40), "dL80": (79, "L0", 80), "dL0": (nf, "L0", 0),
+            "ds1": (nf + 1, "sigma", 1), "ds40": (nf + 40, "sigma", 40), "ds80": (nf + 80, "sigma", 80)}
+    reps = (5, 871)
+
+    def bumped(m, field, n, sgn):
+        mm = model.copy()
+        arr = getattr(mm, field)
+        h = 1e-8 * (arr[n] if field == "L0" else max(arr[n], 0.01))
+        arr[n] += sgn * h
+        return O.price_caplets(mm, N, 1, seed, m_offset=m)[0, -1], h
+
+    jobs = [(m, k, sgn) for m in reps for k in cols for sgn in (1, -1)]
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        res = list(ex.map(lambda j: bumped(j[0], cols[j[1]][1], cols[j[1]][2], j[2]), jobs))
+    val = {(m, k, sgn): r for (m, k, sgn), r in zip(jobs, res)}
+    for m in reps:
+        fd = {k: (val[(m, k, 1)][0] - val[(m, k, -1)][0]) / (2 * val[(m, k, 1)][1]) for k in cols}
+        scale = max(abs(v) for v in fd.values())
+        for k, (col, _, _) in cols.items():
+            e32 = abs(g32[m, col] - fd[k]) / scale
+            e64 = abs(g64[m, col] - fd[k]) / scale
+            _say("full size", m, k, "fd", fd[k], "fp32 err", e32, "fp64 err", e64)
+            assert e64 < 2e-3 and e32 < 2e-3, (m, k)
