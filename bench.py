@@ -71,11 +71,17 @@ PRICE_SOURCES = ("rq_lmm.h", "rq_lmm.hip", "rq_device.h", "rq_internal.h")
 
 
 def _kernel_source_hash(names) -> str:
+    """Hash of the kernel sources' code: comments, blank lines and trailing
+    spaces are dropped first (the sources hold no comment markers inside
+    string literals), so a profile stays matched across comment edits."""
     import hashlib
+    import re
     m = hashlib.sha256()
     for name in names:
-        with open(os.path.join(ROOT, "paper_1408_5526_amd", "csrc", name), "rb") as f:
-            m.update(f.read())
+        with open(os.path.join(ROOT, "paper_1408_5526_amd", "csrc", name)) as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        lines = (re.sub(r"//.*", "", ln).rstrip() for ln in text.split("\n"))
+        m.update("\n".join(ln for ln in lines if ln).encode())
     return m.hexdigest()[:16]
 
 

@@ -39,10 +39,11 @@
 // final states per task) and their payoffs and reverse sweeps in a second;
 // the batch does the same per window of its work items (and runs whole
 // tasks without Greeks for its prices).  State and adjoint state live in
-// registers, the vega
-// accumulators in LDS ([forward][lane], conflict-free; before the sweep the
-// same rows hold the payoff adjoint).  Outputs are wave sums (transpose
-// butterfly), one partial row per path block: deterministic.
+// registers, the vega accumulators in LDS ([forward][lane], conflict-free;
+// before the sweep the same rows hold the payoff adjoint; in the FP32
+// reverse half at capacity 80 the two top forwards' accumulators are
+// registers, to leave LDS room for the drift constants).  Outputs are wave
+// sums (transpose butterfly), one partial row per path block: deterministic.
 #pragma once
 
 #include <type_traits>
@@ -551,8 +552,8 @@ void lmm_adj_fwd_kernel(LmmArgs a)
     lmm_task<NFC, D, T, true, MC, kTaskFwd>(a, m, blk, task, wt, vbar, xs, c6s);
 }
 
-// FP32: the compiler is asked for two waves per SIMD (at most 256 registers);
-// the few values it then spills are outside the time loops.
+// FP32: the compiler is asked for two waves per SIMD (at most 256 registers;
+// the sweep takes about 195, without spills); FP64: one.
 template <int NFC, int D, typename T, bool MC>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
 void lmm_adj_rev_kernel(LmmArgs a)
