@@ -356,71 +356,89 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         for (int n = lane; n < NFC; n += kWave) c6s[n] = tab[n * kAdjRow + 6];
         __syncthreads();
     }
-    T wn[D];
-#pragma unroll
-    for (int f = 0; f < D; ++f) wn[f] = wt[(size_t)((nf - 1) * D + f) * kWave];
-#pragma unroll 1
-    for (int k = nf - 1; k >= 0; --k) {
+    // The state rebuild and adjoint of one forward-step come in two parts, so
+    // that two independent forward-steps can share a wait:
+    //  * incr() forms the increment e = log2(e) (c_n + a_n . w_n) as the
+    //    forward pass forms it (c6 = log2(e) c_n: in FP32 a vector operand
+    //    read from LDS, so that the first FMA takes it beside the row's scalar
+    //    loading);
+    //  * rest() takes forward n from there with a chain's state (w = w_n on
+    //    entry, w_{n-1} on exit; Wbar) and returns the new sigma-scaled vega
+    //    entry vb + term.  on = 0 (masked form) leaves everything unchanged.
+    struct Chain {
         T w[D], Wb[D];
+    };
+    auto incr = [&](const Chain &c, const auto &q, T c6) __attribute__((always_inline)) -> T {
+        T e = ffma(q[0], c.w[0], c6);
+#pragma unroll
+        for (int f = 1; f < D; ++f) e = ffma(q[f], c.w[f], e);
+        return e;
+    };
+    auto rest = [&](Chain &c, int n, const auto &q, T vb, T e, T on, auto masked) __attribute__((always_inline)) -> T {
+        constexpr bool MASKED = decltype(masked)::value;
+        const T y = MASKED ? ffma(-e, on, X[n]) : X[n] - e;
+        X[n] = y;
+        const T g = G(y, q[7]);
+        const T ge = MASKED ? g * on : g;
+        const T xb = MASKED ? Xb[n] * on : Xb[n];
+#pragma unroll
+        for (int f = 0; f < D; ++f) c.Wb[f] = ffma(xb, q[f], c.Wb[f]);
+        T da = q[3] * c.Wb[0];                      // delta a_n . Wbar
+#pragma unroll
+        for (int f = 1; f < D; ++f) da = ffma(q[3 + f], c.Wb[f], da);
+        const T h = ge * da;
+        const T vnew = vb + ffma(xb, e + q[6], h);   // P + 2 log2(e) c_n = e + log2(e) c_n
+        Xb[n] = ffma(kLn2, ffma(-g, h, h), Xb[n]);
+#pragma unroll
+        for (int f = 0; f < D; ++f) c.w[f] = ffma(-ge, q[3 + f], c.w[f]);
+        return vnew;
+    };
+    // Final w of the next two steps to run, loaded a step (or pair) ahead.
+    T wp0[D] = {}, wp1[D] = {};
+    auto load_w = [&](T(&dst)[D], int k) {
+        if (k >= 0) {
+#pragma unroll
+            for (int f = 0; f < D; ++f) dst[f] = wt[(size_t)(k * D + f) * kWave];
+        }
+    };
+    auto take = [&](Chain &c, const T(&src)[D]) {
 #pragma unroll
         for (int f = 0; f < D; ++f) {
-            w[f] = wn[f];
-            Wb[f] = T(0);
+            c.w[f] = src[f];
+            c.Wb[f] = T(0);
         }
-        if (k > 0) {   // prefetch the next (earlier) step's final w
-#pragma unroll
-            for (int f = 0; f < D; ++f) wn[f] = wt[(size_t)((k - 1) * D + f) * kWave];
-        }
-        // adjoint of one forward-step, w = w_n on entry, w_{n-1} on exit;
-        // on = 0 leaves everything unchanged.  q is the forward's table row,
-        // vb its (sigma-scaled) vega entry so far and c6 its drift constant
-        // log2(e) c_n (in FP32 a vector operand read from LDS, so that the
-        // increment's first FMA takes it beside the row's scalar loading).  pre() runs right
-        // after the row's first use, once the wave has waited for the row: it
-        // issues the next forward's row and vega loads and stores the previous
-        // forward-step's vega entry, so that the one wait per forward-step
-        // finds all three long done.
+    };
+    load_w(wp0, nf - 1);
+    load_w(wp1, nf - 2);
+    const NoPre none;
+
+    // One step k alone (FP64 always; FP32 for the first step when n_fwd is
+    // odd).  In FP32 the wholly alive groups come first (unmasked), the group
+    // holding forward k last, as in the forward pass but in reverse order;
+    // the live groups' rows, vega entries and drift constants are
+    // software-pipelined (rr, vo and co hold the next forward's), and pre()
+    // runs right after the row's first use, once the wave has waited for it:
+    // it issues the next forward's loads and stores the previous forward-step's
+    // vega entry, so that the one wait per forward-step finds them long done.
+    auto one_step = [&](Chain &c, int k) __attribute__((always_inline)) {
         T pend = T(0);   // the previous unmasked forward-step's new vega entry, not yet stored
         const int nfk = opaque_u(nf);   // tests on it stay inside the step loop
         auto body = [&](int n, const auto &q, T vb, T c6, T on, auto masked, auto pre) __attribute__((always_inline)) {
             constexpr bool MASKED = decltype(masked)::value;
-            // the increment e = log2(e) (c_n + a_n . w_n), formed as the
-            // forward pass forms it
-            T e = ffma(q[0], w[0], c6);
-#pragma unroll
-            for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
+            const T e = incr(c, q, c6);
             if constexpr (!std::is_same<decltype(pre), NoPre>::value) {
                 __builtin_amdgcn_sched_barrier(0);
                 pre();
                 __builtin_amdgcn_sched_barrier(0);
             }
-            const T y = MASKED ? ffma(-e, on, X[n]) : X[n] - e;
-            X[n] = y;
-            const T g = G(y, q[7]);
-            const T ge = MASKED ? g * on : g;
-            const T xb = MASKED ? Xb[n] * on : Xb[n];
-#pragma unroll
-            for (int f = 0; f < D; ++f) Wb[f] = ffma(xb, q[f], Wb[f]);
-            T da = q[3] * Wb[0];                      // delta a_n . Wbar
-#pragma unroll
-            for (int f = 1; f < D; ++f) da = ffma(q[3 + f], Wb[f], da);
-            const T h = ge * da;
-            const T vnew = vb + ffma(xb, e + q[6], h);   // P + 2 log2(e) c_n = e + log2(e) c_n
+            const T vnew = rest(c, n, q, vb, e, on, masked);
             if constexpr (MASKED || std::is_same<decltype(pre), NoPre>::value)
                 vset(n, vnew);
             else
                 pend = vnew;   // written by the next forward-step, after its wait
-            Xb[n] = ffma(kLn2, ffma(-g, h, h), Xb[n]);
-#pragma unroll
-            for (int f = 0; f < D; ++f) w[f] = ffma(-ge, q[3 + f], w[f]);
         };
-        const NoPre none;
         const unsigned alive = (unsigned)(nf - k);
         if constexpr (kF32) {
-            // wholly alive groups first (unmasked), the group holding forward k
-            // last (masked), as in the forward pass but in reverse order.  The
-            // live groups' rows, vega entries and drift constants are
-            // software-pipelined: rr, vo and co hold the next forward's.
             const lds_ptr<T> c6k = lds_base(c6s);
             T rr[kAdjRow] = {};
             T vo = T(0), co = T(0);
@@ -498,6 +516,139 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     const cptr<T> q = tab + n * kAdjRow;
                     body(n, q, vget(n), q[6], T(1), std::false_type{}, none);
                 }
+        }
+    };
+
+    if constexpr (!kF32) {
+#pragma unroll 1
+        for (int k = nf - 1; k >= 0; --k) {
+            Chain c;
+            take(c, wp0);
+#pragma unroll
+            for (int f = 0; f < D; ++f) wp0[f] = wp1[f];
+            load_w(wp1, k - 2);
+            one_step(c, k);
+        }
+    } else {
+        static_assert(kGrp == 4, "the paired sweep's boundary group is written for groups of four");
+        int k = nf - 1;
+        if (nf & 1) {
+            Chain c;
+            take(c, wp0);
+#pragma unroll
+            for (int f = 0; f < D; ++f) wp0[f] = wp1[f];
+            load_w(wp1, k - 2);
+            one_step(c, k);
+            --k;
+        }
+        // Then two steps at a time: the leading chain runs step kp, the
+        // trailing chain step kp - 1 one forward behind it.  Each slot of the
+        // wholly alive groups holds the leading chain's forward-step n and the
+        // trailing chain's n + 1, independent work that shares one wait; the
+        // trailing chain takes forward n + 1's row and drift constant from the
+        // slot before and the leading chain's new vega entry from a register,
+        // so only the trailing chain writes vega rows (after the next wait).
+#pragma unroll 1
+        for (int kp = k; kp >= 1; kp -= 2) {
+            Chain cL, cT;
+            take(cL, wp0);
+            take(cT, wp1);
+            load_w(wp0, kp - 2);
+            load_w(wp1, kp - 3);
+            const int nfk = opaque_u(nf);
+            const unsigned aliveL = (unsigned)(nf - kp);
+            const lds_ptr<T> c6k = lds_base(c6s);
+            T rr[kAdjRow] = {}, qT[kAdjRow] = {};
+            T vo = T(0), co = T(0), c6T = T(0), vbT = T(0), pendT = T(0);
+#pragma unroll
+            for (int gq = NFC / kGrp - 1; gq >= 0; --gq) {
+                const int n0 = gq * kGrp;
+                if ((unsigned)(n0 - kp) < aliveL) {                         // kp <= n0 < n_fwd
+                    const bool top = n0 + kGrp >= nfk;                      // highest live group
+                    if (top) {
+                        load_row(rr, tab + (n0 + kGrp - 1) * kAdjRow);
+                        vo = vget(n0 + kGrp - 1);
+                        co = c6k[n0 + kGrp - 1];
+                    }
+#pragma unroll
+                    for (int u = kGrp - 1; u >= 0; --u) {
+                        const int n = n0 + u;
+                        T q[kAdjRow];
+#pragma unroll
+                        for (int e = 0; e < kAdjRow; ++e) q[e] = rr[e];
+                        const T vbL = vo, c6L = co;
+                        // the trailing chain at n + 1: none in the first slot
+                        const bool hasT = n + 1 < NFC && !(top && u == kGrp - 1);
+                        const T eL = incr(cL, q, c6L);
+                        T eT = T(0);
+                        if (hasT) eT = incr(cT, qT, c6T);
+                        __builtin_amdgcn_sched_barrier(0);
+                        {
+                            const cptr<T> t2 = after(tab, q[0]);
+                            __builtin_amdgcn_sched_barrier(0);
+                            if (n > 0) {
+                                load_row(rr, t2 + (n - 1) * kAdjRow);
+                                vo = vget(n - 1);
+                                co = c6k[n - 1];
+                            }
+                            // the trailing chain's entry of forward n + 2, from the
+                            // slot before the previous one (none in the first two)
+                            if (n + 2 < NFC && !(top && u >= kGrp - 2)) vset(n + 2, pendT);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                        const T vnL = rest(cL, n, q, vbL, eL, T(1), std::false_type{});
+                        if (hasT) pendT = rest(cT, n + 1, qT, vbT, eT, T(1), std::false_type{});
+#pragma unroll
+                        for (int e = 0; e < kAdjRow; ++e) qT[e] = q[e];
+                        c6T = c6L;
+                        vbT = vnL;
+                    }
+                    if (n0 - kGrp < kp) {
+                        // the lowest such group: the trailing chain's forward n0
+                        vset(n0 + 1, pendT);
+                        const T eT = incr(cT, qT, c6T);
+                        vset(n0, rest(cT, n0, qT, vbT, eT, T(1), std::false_type{}));
+                    }
+                }
+            }
+            // The group holding forward kp (n0 < kp <= n0 + 4, r = kp - n0):
+            // forward n0 + 3 is the leading chain's if r <= 3 (masked) and the
+            // trailing chain's always; n0 + 2 the leading chain's if r <= 2 and
+            // the trailing chain's if r <= 3; n0 + 1 likewise with r <= 1 and
+            // r <= 2; n0 the trailing chain's if r = 1.  Uniform branches skip
+            // the levels no chain needs; each level runs the leading chain's
+            // forward-step (masked), then the trailing chain's (unmasked; a
+            // forward beyond the model has a zero row and is a no-op).
+#pragma unroll
+            for (int gq = NFC / kGrp - 1; gq >= 0; --gq) {
+                const int n0 = gq * kGrp;
+                if ((unsigned)(kp - n0 - 1) < (unsigned)kGrp) {
+                    const int r = kp - n0;
+                    T qg[kGrp][kAdjRow];
+#pragma unroll
+                    for (int u = 1; u < kGrp; ++u) load_row(qg[u], tab + (n0 + u) * kAdjRow);
+                    const Quad<T> c4 = lds_quad(c6k, n0);
+                    auto level = [&](int u) __attribute__((always_inline)) {
+                        const int n = n0 + u;
+                        const T on = __builtin_bit_cast(
+                            float, __builtin_amdgcn_readfirstlane(n >= kp ? 0x3f800000u : 0u));
+                        vset(n, rest(cL, n, qg[u], vget(n), incr(cL, qg[u], c4.v[u]), on, std::true_type{}));
+                        vset(n, rest(cT, n, qg[u], vget(n), incr(cT, qg[u], c4.v[u]), T(1), std::false_type{}));
+                    };
+                    level(3);
+                    if (r <= 3) {
+                        level(2);
+                        if (r <= 2) {
+                            level(1);
+                            if (r <= 1) {
+                                load_row(qg[0], tab + n0 * kAdjRow);
+                                vset(n0, rest(cT, n0, qg[0], vget(n0), incr(cT, qg[0], c4.v[0]), T(1),
+                                              std::false_type{}));
+                            }
+                        }
+                    }
+                }
+            }
         }
     }
 
