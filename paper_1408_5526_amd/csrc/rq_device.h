@@ -107,7 +107,12 @@ __device__ __forceinline__ double radinv_R(const PointCtx &c, const StartEnt &e,
     const double rhi = __builtin_fma(carry ? 1.0 : 0.0, e.drhi, e.rhi0);
     double v = (double)vi;
     double R = 0.0;
-    if (!PERM) {
+    if (!PERM && c.L == 2) {
+        // two low digits (p^2 >= N, most dimensions): v < p^2, so v = q1 p + a1
+        // with q1 = floor(v/p) < p, and the reversal is a1 p + q1, no loop
+        const double q1 = __builtin_trunc(v * c.invp);
+        R = __builtin_fma(__builtin_fma(-q1, c.pd, v), c.pd, q1);
+    } else if (!PERM) {
         uint32_t q = 0;
         for (; q + 2 <= c.L; q += 2) {
             const double q1 = __builtin_trunc(v * c.invp);
