@@ -62,9 +62,14 @@ SMOOTH = [
     ("nf12d2-mc", lambda: I.lmm_curve80(12, 2), 300, 2, 6, rq.MC_PHILOX),
     ("nf12d2-permrep", lambda: I.lmm_curve80(12, 2), 300, 2, 6, rq.PERM_PER_REP),
     # edge shapes of the grouped sweeps: one forward; two forwards, two
-    # factors; one past a capacity boundary (17 -> 32); a ragged last block
+    # factors; one past a capacity boundary (17 -> 32); a ragged last block.
+    # The FP32 sweep runs steps in pairs after a lone first step when n_fwd
+    # is odd: 3, 4 and 5 forwards put the pairs' last group at every offset
     ("nf1d1", lambda: I.lmm_curve80(1, 1), 200, 2, 11),
     ("nf2d2", lambda: I.lmm_curve80(2, 2), 130, 2, 12),
+    ("nf3d3", lambda: I.lmm_curve80(3, 3), 200, 2, 14),
+    ("nf4d1", lambda: I.lmm_curve80(4, 1), 150, 2, 15),
+    ("nf5d2", lambda: I.lmm_curve80(5, 2), 180, 2, 16),
     ("nf17d3", lambda: I.lmm_curve80(17, 3), 333, 2, 13),
     # rates 1e-4..15%, vols to 120%, two zero vols (carried as 2^-60)
     ("stress", I.lmm_stress, 300, 2, 22),
