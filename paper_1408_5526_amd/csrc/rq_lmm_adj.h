@@ -118,13 +118,14 @@ constexpr int rev_reg_rows()
     return sizeof(T) == 4 && over > 0 ? (over + kWave * (int)sizeof(T) - 1) / (kWave * (int)sizeof(T)) : 0;
 }
 
-template <int NFC, int D, typename T, bool GREEKS, bool MC, int PART = kTaskWhole, int VR = 0>
+template <int NFC, int D, typename T, bool GREEKS, bool MC, int PART = kTaskWhole, int VR = 0, int XL = 0>
 __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64_t task, T *__restrict__ wt,
                                          T (*__restrict__ vbar)[kWave], T *__restrict__ xs = nullptr,
-                                         T *__restrict__ c6s = nullptr)
+                                         T *__restrict__ c6s = nullptr, T (*__restrict__ xl)[kWave] = nullptr)
 {
     static_assert(NFC % 16 == 0 && NFC % kGrp == 0, "capacity must be a multiple of 16");
     static_assert(VR >= 0 && VR < kGrp, "at most kGrp - 1 vega rows in registers");
+    static_assert(XL == 0 || (PART == kTaskFwd && XL % kGrp == 0 && XL < NFC), "LDS states: forward halves only");
     constexpr bool kF32 = sizeof(T) == 4;
     constexpr T kLn2 = T(0.69314718055994530942);
     const int lane = threadIdx.x;
@@ -145,6 +146,15 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     const StartEnt *__restrict__ st = a.g.starts + ((size_t)m * a.g.n_seg + seg) * a.g.s;
 
     T X[NFC], Xb[NFC];
+    // state of forward n: X[n], or in the forward half the LDS row xl[n]
+    // for the XL lowest forwards (forward n moves in steps 0..n only, so these
+    // take few of the forward-steps; their registers go to a fifth wave per
+    // SIMD).  n is a compile-time constant at every use.
+    auto xget = [&](int n) -> T { return n < XL ? xl[n][lane] : X[n]; };
+    auto xset = [&](int n, T v) {
+        if (n < XL) xl[n][lane] = v;
+        else X[n] = v;
+    };
     // vega row n: vbar[n][lane], or a register for n >= kLdsRows (n is a
     // compile-time constant at every use, in unrolled loops)
     constexpr int kLdsRows = NFC - VR;
@@ -155,7 +165,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         else vbar[n][lane] = v;
     };
 #pragma unroll
-    for (int n = 0; n < NFC; ++n) X[n] = PART == kTaskRev ? xs[n * kWave] : T(0);
+    for (int n = 0; n < NFC; ++n) xset(n, PART == kTaskRev ? xs[n * kWave] : T(0));
     if constexpr (PART != kTaskRev) {
         // the drift constants log2(e) c_n, broadcast from LDS (c6s, NFC
         // entries): a forward-step's first FMA then takes one scalar operand
@@ -197,7 +207,8 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         // constant log2(e) c_n, read from LDS
         auto body = [&](int n, T c6) __attribute__((always_inline)) {
             const cptr<T> q = tab + n * kAdjRow;
-            const T g = G(X[n], q[7]);
+            const T xn = xget(n);
+            const T g = G(xn, q[7]);
 #pragma unroll
             for (int f = 0; f < D; ++f) w[f] = ffma(g, q[3 + f], w[f]);
             // the (small) increment log2(e) (c_n + a_n . w) is formed first and
@@ -205,7 +216,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             T e = ffma(q[0], w[0], c6);
 #pragma unroll
             for (int f = 1; f < D; ++f) e = ffma(q[f], w[f], e);
-            X[n] += e;
+            xset(n, xn + e);
         };
         const unsigned alive = (unsigned)(nf - k);
         const lds_ptr<T> c6k = lds_base(c6s);
@@ -246,7 +257,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 
     if constexpr (PART == kTaskFwd) {
 #pragma unroll
-        for (int n = 0; n < NFC; ++n) xs[n * kWave] = X[n];
+        for (int n = 0; n < NFC; ++n) xs[n * kWave] = xget(n);
         return;
     }
 
@@ -688,19 +699,29 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 //  * lmm_adj_rev_kernel loads the final states and runs the payoffs and the
 //    reverse sweep with the vega rows in LDS, at two waves per SIMD (X and
 //    Xbar in registers).
+// Forward states held in LDS by the FP32 forward half: the 16 lowest
+// forwards' at capacity 80 (a fifth wave per SIMD), none below
+template <int NFC, typename T>
+constexpr int fwd_lds_states()
+{
+    return sizeof(T) == 4 && NFC == 80 ? 16 : 0;
+}
+
 template <int NFC, int D, typename T, bool MC>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(fwd_lds_states<NFC, T>() ? 5 : sizeof(T) == 4 ? 4 : 2)))
 void lmm_adj_fwd_kernel(LmmArgs a)
 {
+    constexpr int XL = fwd_lds_states<NFC, T>();
     __shared__ T vbar[NFC][kWave];   // not touched by the forward half
     __shared__ __align__(32) T c6s[NFC];
+    __shared__ T xl[XL > 0 ? XL : 1][kWave];
     const int64_t local = blockIdx.x;
     const int64_t task = a.task0 + local;
     const int m = (int)(task / a.n_blk);
     const int blk = (int)(task - (int64_t)m * a.n_blk);
     T *wt = (T *)a.wtop + local * ((int64_t)a.n_fwd * D * kWave) + threadIdx.x;
     T *xs = (T *)a.xs + local * ((int64_t)NFC * kWave) + threadIdx.x;
-    lmm_task<NFC, D, T, true, MC, kTaskFwd>(a, m, blk, task, wt, vbar, xs, c6s);
+    lmm_task<NFC, D, T, true, MC, kTaskFwd, 0, XL>(a, m, blk, task, wt, vbar, xs, c6s, xl);
 }
 
 // FP32: the compiler is asked for two waves per SIMD (at most 256 registers;
