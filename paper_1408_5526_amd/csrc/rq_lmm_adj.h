@@ -693,9 +693,10 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
 // Single-call adjoint, two kernels per chunk of tasks (task = m n_blk + blk,
 // one 64-path wave per block, one block per task):
 //  * lmm_adj_fwd_kernel runs the forward passes.  Its state is the 80
-//    forwards and w only, so it runs at four waves per SIMD in FP32 (the
-//    point generation and the forward-steps hide each other's latencies);
-//    it stores w per step and the final states, 82 KB per task in FP32.
+//    forwards (the 16 lowest in LDS at capacity 80) and w only, so it runs
+//    at five waves per SIMD in FP32 (the point generation and the
+//    forward-steps hide each other's latencies); it stores w per step and
+//    the final states, 82 KB per task in FP32.
 //  * lmm_adj_rev_kernel loads the final states and runs the payoffs and the
 //    reverse sweep with the vega rows in LDS, at two waves per SIMD (X and
 //    Xbar in registers).
