@@ -24,12 +24,13 @@
 
 namespace rq {
 
-// Waves per SIMD asked of the compiler: FP32 phase 1 (forward halves and
-// MBS items) four, FP32 phases 0 and 2 two (their payoff and adjoint state
-// need the registers); FP64 one.
+// Waves per SIMD asked of the compiler: FP32 phase 1 (forward halves, the
+// 24 lowest forwards' states in LDS, and MBS items) five (a few values
+// spilled; 4% faster than four), FP32 phases 0 and 2 two (their payoff and
+// adjoint state need the registers); FP64 one.
 template <typename T, bool GREEKS, int PHASE>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(
-    sizeof(T) == 4 ? (PHASE == 1 ? 4 : 2) : 1)))
+    sizeof(T) == 4 ? (PHASE == 1 ? 5 : 2) : 1)))
 void batch_kernel(BatchArgs b)
 {
     constexpr int part = PHASE == 1 ? kTaskFwd : PHASE == 2 ? kTaskRev : kTaskWhole;
@@ -38,6 +39,8 @@ void batch_kernel(BatchArgs b)
     constexpr int VR = PHASE == 2 ? rev_reg_rows<kMaxFwd, T>() : 0;
     constexpr bool kC6 = !(PHASE == 2 && sizeof(T) == 8);
     __shared__ T vbar[kMaxFwd - VR][kWave];
+    constexpr int XL = PHASE == 1 && sizeof(T) == 4 ? 24 : 0;   // forward states in LDS (phase 1)
+    __shared__ T xl[XL > 0 ? XL : 1][kWave];
     __shared__ __align__(32) T c6s[kC6 ? kMaxFwd : 1];
     const int lane = threadIdx.x;
     const cptr<int64_t> item0 = as_const<int64_t>(b.item0);
@@ -73,12 +76,12 @@ void batch_kernel(BatchArgs b)
                 const int sel = inst[lo].n_factors * 2 + (a.g.mc ? 1 : 0);
                 T *c6p = kC6 ? &c6s[0] : nullptr;
                 switch (sel) {
-                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
-                default: lmm_task<kMaxFwd, 3, T, GREEKS, false, part, VR>(a, m, blk, local, wt, vbar, xs, c6p); break;
+                case 2: lmm_task<kMaxFwd, 1, T, GREEKS, false, part, VR, XL>(a, m, blk, local, wt, vbar, xs, c6p, xl); break;
+                case 3: lmm_task<kMaxFwd, 1, T, GREEKS, true, part, VR, XL>(a, m, blk, local, wt, vbar, xs, c6p, xl); break;
+                case 4: lmm_task<kMaxFwd, 2, T, GREEKS, false, part, VR, XL>(a, m, blk, local, wt, vbar, xs, c6p, xl); break;
+                case 5: lmm_task<kMaxFwd, 2, T, GREEKS, true, part, VR, XL>(a, m, blk, local, wt, vbar, xs, c6p, xl); break;
+                case 7: lmm_task<kMaxFwd, 3, T, GREEKS, true, part, VR, XL>(a, m, blk, local, wt, vbar, xs, c6p, xl); break;
+                default: lmm_task<kMaxFwd, 3, T, GREEKS, false, part, VR, XL>(a, m, blk, local, wt, vbar, xs, c6p, xl); break;
                 }
             } else if (PHASE != 2) {
                 const MbsArgs a = load_uniform<MbsArgs>(&b.inst[lo].mbs);
