@@ -45,23 +45,24 @@ namespace rq {
 // pseudo-random points (the comparison baseline).  EULER: the plain Euler
 // step of the paper's discretised SDE instead of the log-Euler step,
 //   L_n <- L_n + mu_n L_n delta + L_n sqrt(delta) a_n . z_k = L_n (1 + a_n . w).
-// Occupancy hints: FP32 Halton forms at four waves per SIMD, five at
-// capacity 80 (the 24 lowest forwards' states then live in LDS: forward n
-// moves in steps 0..n only, so they take few of the forward-steps, and their
-// registers go to the fifth wave; a few values are still spilled, and the
-// kernel is 7% faster than at four waves); FP64 Halton forms at two (256 registers:
-// the 80 FP64 forwards take 160 of them, and the second wave hides the
-// latency of the long dependent FP64 chains of the drift factor, the
-// exponential and the digits); Philox forms at the compiler's choice.
+// Occupancy hints: FP32 forms at five waves per SIMD at capacity 80 (the
+// 24 lowest forwards' states then live in LDS: forward n moves in steps
+// 0..n only, so they take few of the forward-steps, and their registers go
+// to the fifth wave; a few values are still spilled, and the kernel is 7%
+// (Halton) and 4% (Philox) faster than at four waves); below capacity 80 the
+// FP32 Halton forms at four; FP64 Halton forms at two (256 registers: the 80
+// FP64 forwards take 160 of them, and the second wave hides the latency of
+// the long dependent FP64 chains of the drift factor, the exponential and
+// the digits); Philox forms otherwise at the compiler's choice.
 template <int NFC, typename T, int GEN>
 constexpr int price_lds_states()
 {
-    return sizeof(T) == 4 && GEN != 2 && NFC == 80 ? 24 : 0;
+    return sizeof(T) == 4 && NFC == 80 ? 24 : 0;
 }
 
 template <int NFC, int D, typename T, int GEN, bool EULER = false>
 __global__ __launch_bounds__(kBlock)
-__attribute__((amdgpu_waves_per_eu(GEN == 2 ? 1 : price_lds_states<NFC, T, GEN>() ? 5 : (sizeof(T) == 4 ? 4 : 2))))
+__attribute__((amdgpu_waves_per_eu(price_lds_states<NFC, T, GEN>() ? 5 : GEN == 2 ? 1 : (sizeof(T) == 4 ? 4 : 2))))
 void lmm_kernel(LmmArgs a)
 {
     static_assert(NFC % 16 == 0, "capacity must be a multiple of 16");
