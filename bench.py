@@ -196,7 +196,21 @@ def generator_leg(rq, torch, dev, steps: int):
         _, kms, _ = _time_steps(lambda: rq.sequence(s, n, m, 5, flags, device=dev, out=buf, ws=ws), steps, 1)
         out[name + "_gnumbers_per_s"] = s * n * m / (kms / 1e3) / 1e9
         out[name + "_kernel_ms"] = kms
+        out[name + "_write_tb_s"] = s * n * m * 8 / (kms / 1e3) / 1e12
         del buf, ws
+    # a plain write of the same bytes (torch's fill kernel), for the rate that
+    # writes alone reach on this device beside the published 8 TB/s
+    buf = torch.empty((m, n, s), dtype=torch.float64, device=dev)
+    buf.fill_(0.0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        buf.fill_(1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    out["fill_write_tb_s"] = buf.numel() * 8 / (e0.elapsed_time(e1) / steps / 1e3) / 1e12
+    del buf
     out["note"] = ("FP64 digit expansion per number, 8 B written per number; the pricing kernels "
                    "generate the same points in registers and never store them")
     return out
