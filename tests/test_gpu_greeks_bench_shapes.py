@@ -42,9 +42,10 @@ def _say(*a):
 
 
 # (name, n_fwd, n_factors, N, M, seed): 80 and 64 forwards fill their
-# capacities; 57 and 49 leave the top group of 64 partly empty (ragged
-# last block too: N not a multiple of 64)
+# capacities; 70, 57 and 49 leave the top groups of 80 and 64 partly empty
+# (ragged last block too: N not a multiple of 64)
 FULL = [("nf80d3", 80, 3, 256, 2, 31), ("nf64d3", 64, 3, 200, 2, 32),
+        ("nf70d3", 70, 3, 192, 1, 36),
         ("nf57d3", 57, 3, 130, 1, 33), ("nf49d2", 49, 2, 256, 1, 34)]
 
 

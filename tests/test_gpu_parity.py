@@ -146,6 +146,7 @@ LMM = [
     ("nf6d2-ragged", lambda: I.small_lmm(6, 2), 1000, 3, 17, 0),
     ("nf20d3", lambda: I.lmm_curve80(20, 3), 513, 2, 5, 0),
     ("nf80d3", lambda: I.lmm_curve80(), 300, 2, 3, 0),
+    ("nf71d2", lambda: I.lmm_curve80(71, 2), 300, 2, 6, 0),      # capacity 80, top group partly empty
     ("nf33d1-perm", lambda: I.lmm_curve80(33, 1), 257, 2, 9, rq.PERM_RANDOM),
     ("nf48d2-zero", lambda: I.lmm_curve80(48, 2), 256, 1, 4, rq.START_ZERO),
     ("nf1", _one_fwd, 100, 2, 3, 0),
@@ -186,6 +187,10 @@ LMM32 = [
     ("nf6d2-ragged", lambda: I.small_lmm(6, 2), 4133, 3, 17, 0),
     ("nf20d3", lambda: I.lmm_curve80(20, 3), 4200, 2, 5, 0),
     ("nf80d3", lambda: I.lmm_curve80(), 4133, 2, 3, 0),
+    # capacity 80 below its top: the FP32 form keeps the 24 lowest forwards'
+    # states in LDS there, with Halton and with Philox points
+    ("nf71d2", lambda: I.lmm_curve80(71, 2), 4133, 2, 6, 0),
+    ("nf67d3-mc", lambda: I.lmm_curve80(67, 3), 4133, 2, 7, rq.MC_PHILOX),
     ("nf33d1-perm", lambda: I.lmm_curve80(33, 1), 4097, 2, 9, rq.PERM_RANDOM),
     ("nf20d3-mc", lambda: I.lmm_curve80(20, 3), 4200, 2, 5, rq.MC_PHILOX),
     ("nf33d1-permrep", lambda: I.lmm_curve80(33, 1), 4097, 3, 9, rq.PERM_PER_REP),
