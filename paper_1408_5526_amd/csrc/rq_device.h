@@ -257,7 +257,7 @@ __device__ __forceinline__ double inv_normal(double u, double)
 // branch runs only in waves that hold a tail point (~20% of waves).
 __device__ __forceinline__ float inv_normal(double u, float)
 {
-    const double p = u * (1.0 - u);
+    const double p = __builtin_fma(-u, u, u);   // u (1 - u), rounded once
     const float pf = fmaxf((float)p, 0x1p-64f);
     const float w = __builtin_fmaf(__builtin_amdgcn_logf(pf), -0.693147180559945309f,
                                    -1.38629436111989062f);   // -ln(4 p)
