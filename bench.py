@@ -332,7 +332,7 @@ def batch_leg(rq, I, torch, dev, n_cap: int, m_cap: int, steps: int, autotune: b
     if autotune:
         t0 = time.perf_counter()
         (chunk, per_cu, order), tms = rq.autotune_batch(insts, "fp32", greeks=True, device=dev, ws=ws)
-        tune = {"chunk": chunk, "waves_per_cu": per_cu,
+        tune = {"chunk": chunk or "automatic", "waves_per_cu": per_cu or "resident",
                 "order": "cost" if order == rq.ORDER_COST else "given",
                 "autotune_ms": tms, "autotune_wall_s": time.perf_counter() - t0}
     used, from_tuner = rq.batch_tuning(insts, "fp32", greeks=True)

@@ -318,13 +318,15 @@ rq_status rq_price_batch(const rq_instrument *inst, int n_inst, rq_precision pre
                          uint64_t *t_first, uint64_t *t_last, void *ws, size_t ws_bytes, void *stream);
 
 /* autotune_batch: the project's launch-shape autotuner for price_batch.
- * Candidates: chunk (work items per queue grab) in {1, 2, 4, 8, 16} x
- * waves_per_cu in {the resident count, half of it} x both orders (20
- * shapes).  After one untimed run it times every candidate once; a batch of
- * more than 2^28 paths is screened on a probe of itself (each instrument's
- * M divided by the power of two that brings the probe near 2^28 paths, at
- * least 1) and the three fastest shapes there are timed on the full batch
- * (after one untimed full run).  The fastest shape is returned in *best
+ * Candidates: the automatic shape (all zero) in both orders, and chunk
+ * (work items per queue grab) in {1, 2, 4, 8, 16} x waves_per_cu in {the
+ * resident count, half of it} x both orders (22 shapes).  After one untimed
+ * run it times every candidate once; a batch of more than 2^28 paths is
+ * screened on a probe of itself (each instrument's M divided by the power
+ * of two that brings the probe near 2^28 paths, at least 1) and the three
+ * fastest shapes there, with the automatic one in cost order, are timed on
+ * the full batch (after one untimed full run), so the choice is not slower
+ * than price_batch without a tuning beyond timing noise.  The fastest shape is returned in *best
  * (its full-batch time in ms in *best_ms unless NULL) and kept for this
  * batch's signature (precision, Greeks, and per instrument its kind,
  * shape, N, M and flags): rq_price_batch with tuning == NULL then uses it.

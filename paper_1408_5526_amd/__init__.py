@@ -433,8 +433,9 @@ def price_batch(instruments, precision="fp32", greeks: bool = False, tuning=None
 
 def autotune_batch(instruments, precision="fp32", greeks: bool = False, device=None, ws=None):
     """(chunk, waves_per_cu, order) of the fastest launch shape for this
-    batch, and its time in ms (rq_autotune_batch: 20 candidate shapes, a
-    large batch screened on a probe of itself).  price_batch with
+    batch, and its time in ms (rq_autotune_batch: the automatic shape,
+    (0, 0, order), and 20 fixed ones; a large batch screened on a probe of
+    itself).  price_batch with
     tuning=None then uses the choice for this list."""
     dev = _device(device)
     h = _BatchHost(instruments)

@@ -1550,7 +1550,11 @@ rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision 
     }
     const int occ = rq::batch_blocks_per_cu(prec == RQ_FP32, greeks, greeks ? 2 : 0);
     if (occ <= 0) return fail(RQ_EHIP, "occupancy query of the batch kernel failed");
-    std::vector<rq_tuning> cand;
+    // the automatic shape (chunk from each window's item count, every
+    // resident block) in both orders, then the fixed shapes; cand[0], the
+    // shape rq_price_batch takes without a tuning, is always a finalist, so
+    // the choice is never slower than running untuned (up to timing noise)
+    std::vector<rq_tuning> cand = {rq_tuning{0, 0, RQ_ORDER_COST}, rq_tuning{0, 0, RQ_ORDER_GIVEN}};
     const int chunks[] = {1, 2, 4, 8, 16};
     const int orders[] = {RQ_ORDER_COST, RQ_ORDER_GIVEN};
     std::vector<int> per_cu = {occ};
@@ -1603,14 +1607,18 @@ rq_status rq_autotune_batch(const rq_instrument *inst, int n_inst, rq_precision 
             bt = cand[timed[0].second];
             bms = timed[0].first;
         } else {
-            // the finalists on the full batch, after one untimed full run
-            stt = run_batch(inst, n_inst, prec, greeks, &cand[timed[0].second], outs, grads, nullptr, nullptr, ws,
-                            ws_bytes, st);
-            for (size_t r = 0; stt == RQ_OK && r < std::min<size_t>(3, timed.size()); ++r) {
-                stt = time_one(inst, cand[timed[r].second], ms);
+            // the finalists on the full batch, after one untimed full run:
+            // the probe's three fastest and the automatic shape
+            std::vector<int> fin;
+            for (size_t r = 0; r < std::min<size_t>(3, timed.size()); ++r) fin.push_back(timed[r].second);
+            if (std::find(fin.begin(), fin.end(), 0) == fin.end()) fin.push_back(0);
+            stt = run_batch(inst, n_inst, prec, greeks, &cand[fin[0]], outs, grads, nullptr, nullptr, ws, ws_bytes,
+                            st);
+            for (size_t r = 0; stt == RQ_OK && r < fin.size(); ++r) {
+                stt = time_one(inst, cand[fin[r]], ms);
                 if (stt == RQ_OK && ms < bms) {
                     bms = ms;
-                    bt = cand[timed[r].second];
+                    bt = cand[fin[r]];
                 }
             }
         }

@@ -173,7 +173,9 @@ def test_autotune_picks_a_candidate_and_keeps_results():
     _say("autotune")
     assert rq.batch_tuning(batch, precision="fp32", greeks=True) == ((0, 0, 0), False)
     (chunk, per_cu, order), ms = rq.autotune_batch(batch, precision="fp32", greeks=True)
-    assert chunk in (1, 2, 4, 8, 16) and per_cu >= 1 and order in (rq.ORDER_COST, rq.ORDER_GIVEN) and ms > 0
+    # (0, 0): the automatic shape, which is among the candidates
+    assert (chunk, per_cu) == (0, 0) or (chunk in (1, 2, 4, 8, 16) and per_cu >= 1)
+    assert order in (rq.ORDER_COST, rq.ORDER_GIVEN) and ms > 0
     # kept for this list's signature: price_batch without a tuning uses it
     assert rq.batch_tuning(batch, precision="fp32", greeks=True) == ((chunk, per_cu, order), True)
     assert rq.batch_tuning(batch, precision="fp64", greeks=True)[1] is False
