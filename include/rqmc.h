@@ -200,7 +200,7 @@ rq_status rq_sequence(int s, int64_t N, int M, uint64_t seed, int flags, int64_t
  * scheme; it keeps its state in log2 units, so FP64 prices agree with the
  * pricing kernel's to rounding).  The adjoint runs as two kernels over
  * chunks of 64-path blocks: the forward passes store every step's w and the
- * final states in the workspace (at most 16 GiB, sized by
+ * final states in the workspace (at most 64 GiB, sized by
  * rq_caplets_workspace), then the payoffs and reverse sweeps read them. */
 rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t seed,
                            int64_t m_offset, int flags, rq_precision prec,
@@ -209,7 +209,7 @@ rq_status rq_price_caplets(const rq_lmm_model *model, int64_t N, int M, uint64_t
 
 /* The adjoint's store region (see rq_price_caplets): at most `bytes` per
  * chunk, counted in FP64 (at least one 64-path task per chunk); 0 restores
- * the default, 16 GiB.  Process-wide; it changes the workspace size that
+ * the default, 64 GiB.  Process-wide; it changes the workspace size that
  * rq_caplets_workspace reports for calls with Greeks and the number of
  * kernel launches, never the results (each task's arithmetic and partial
  * row are the same in any chunk).  Set it before sizing the workspace. */

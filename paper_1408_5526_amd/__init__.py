@@ -579,7 +579,7 @@ def timer_end():
 
 def set_adjoint_store_limit(nbytes: int) -> None:
     """Bytes (FP64-counted) of the two-kernel adjoint's store region per
-    chunk of tasks; 0 restores the default (16 GiB).  Results never depend
+    chunk of tasks; 0 restores the default (64 GiB).  Results never depend
     on it; the workspace size does."""
     _check(lib().rq_set_adjoint_store_limit(nbytes))
 

@@ -184,8 +184,11 @@ hipError_t launch_lmm_adjoint(const LmmArgs &a, int n_factors, int fp32, int par
 constexpr int kAdjBlockHost = 64;    // paths per block (task) of the adjoint kernels (one wave)
 constexpr int kAdjSlots = 2048;      // batch adjoint grid: 256 CUs x 8 resident waves
 // Single-call adjoint: bytes of stored w and final states per launch pair,
-// at most (the tasks are processed in chunks that fit).
-constexpr size_t kAdjStoreBytes = (size_t)16 << 30;
+// at most (the tasks are processed in chunks that fit), FP64-counted; the
+// batch's window store likewise.  64 GiB of the 288 GB of HBM: fewer
+// windows, so fewer phase boundaries where the persistent batch grid drains
+// (-2.4% batch time against 16 GiB)
+constexpr size_t kAdjStoreBytes = (size_t)64 << 30;
 hipError_t launch_mbs(const MbsArgs &a, int fp32, hipStream_t st);   // n_part == 2: tangent
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t st);
 hipError_t launch_finalize(const FinalizeArgs &a, hipStream_t st);

@@ -88,7 +88,7 @@ def test_adjoint_store_limit_sizes_the_workspace():
     # the two-kernel adjoint stores w and the final states for one chunk of
     # 64-path tasks: (20 x 3 + 32) x 64 x 8 B = 47,104 B per task counted in
     # FP64; a limit of 7 tasks shrinks the Greeks workspace accordingly, and
-    # 0 restores the default (16 GiB, i.e. all 64 tasks here)
+    # 0 restores the default (64 GiB, i.e. all 64 tasks here)
     m = I.lmm_curve80(20, 3)
     h = rq._LmmHost(m)
     per = (20 * 3 + 32) * 64 * 8
