@@ -111,7 +111,7 @@ def test_adjoint_greeks_match_black_within_se_plus_bias(name, mk, N, M, seed, pr
 
 def test_adjoint_full_size_sampled_replications_match_oracle_fd():
     # The benchmark's launch: the 80-forward, 3-factor book with Greeks at
-    # N = 2^16, M = 1024 (FP32: six chunks of tasks; FP64: eleven).  On two
+    # N = 2^16, M = 1024 (FP32: two chunks of tasks; FP64: three).  On two
     # sampled replications, seven sampled Greeks (deltas of forwards 1, 40
     # and 80, the spot delta, vegas of forwards 1, 40 and 80) against the
     # oracle's central differences of that replication alone (m_offset), the
