@@ -425,8 +425,8 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
     load_w(wp1, nf - 2);
     const NoPre none;
 
-    // One step k alone (FP64 always; FP32 for the first step when n_fwd is
-    // odd).  In FP32 the wholly alive groups come first (unmasked), the group
+    // One step k alone (the first step when n_fwd is odd; the rest run in
+    // pairs below).  In FP32 the wholly alive groups come first (unmasked), the group
     // holding forward k last, as in the forward pass but in reverse order;
     // the live groups' rows, vega entries and drift constants are
     // software-pipelined (rr, vo and co hold the next forward's), and pre()
@@ -532,17 +532,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         }
     };
 
-    if constexpr (!kF32) {
-#pragma unroll 1
-        for (int k = nf - 1; k >= 0; --k) {
-            Chain c;
-            take(c, wp0);
-#pragma unroll
-            for (int f = 0; f < D; ++f) wp0[f] = wp1[f];
-            load_w(wp1, k - 2);
-            one_step(c, k);
-        }
-    } else {
+    {
         static_assert(kGrp == 4, "the paired sweep's boundary group is written for groups of four");
         int k = nf - 1;
         if (nf & 1) {
@@ -561,6 +551,9 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
         // trailing chain takes forward n + 1's row and drift constant from the
         // slot before and the leading chain's new vega entry from a register,
         // so only the trailing chain writes vega rows (after the next wait).
+        // Both precisions: FP64, at one wave per SIMD, has the more latency
+        // to hide (its whole step with Greeks took 13% less time than with
+        // one step at a time; the FP32 reverse half 5% less).
 #pragma unroll 1
         for (int kp = k; kp >= 1; kp -= 2) {
             Chain cL, cT;
@@ -570,7 +563,10 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
             load_w(wp1, kp - 3);
             const int nfk = opaque_u(nf);
             const unsigned aliveL = (unsigned)(nf - kp);
-            const lds_ptr<T> c6k = lds_base(c6s);
+            // drift constants: FP32 from the LDS table (a vector operand),
+            // FP64 from the row's entry 6
+            lds_ptr<T> c6k{};
+            if constexpr (kF32) c6k = lds_base(c6s);
             T rr[kAdjRow] = {}, qT[kAdjRow] = {};
             T vo = T(0), co = T(0), c6T = T(0), vbT = T(0), pendT = T(0);
 #pragma unroll
@@ -581,7 +577,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     if (top) {
                         load_row(rr, tab + (n0 + kGrp - 1) * kAdjRow);
                         vo = vget(n0 + kGrp - 1);
-                        co = c6k[n0 + kGrp - 1];
+                        if constexpr (kF32) co = c6k[n0 + kGrp - 1];
                     }
 #pragma unroll
                     for (int u = kGrp - 1; u >= 0; --u) {
@@ -589,7 +585,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                         T q[kAdjRow];
 #pragma unroll
                         for (int e = 0; e < kAdjRow; ++e) q[e] = rr[e];
-                        const T vbL = vo, c6L = co;
+                        const T vbL = vo, c6L = kF32 ? co : q[6];
                         // the trailing chain at n + 1: none in the first slot
                         const bool hasT = n + 1 < NFC && !(top && u == kGrp - 1);
                         const T eL = incr(cL, q, c6L);
@@ -602,7 +598,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                             if (n > 0) {
                                 load_row(rr, t2 + (n - 1) * kAdjRow);
                                 vo = vget(n - 1);
-                                co = c6k[n - 1];
+                                if constexpr (kF32) co = c6k[n - 1];
                             }
                             // the trailing chain's entry of forward n + 2, from the
                             // slot before the previous one (none in the first two)
@@ -640,13 +636,21 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                     T qg[kGrp][kAdjRow];
 #pragma unroll
                     for (int u = 1; u < kGrp; ++u) load_row(qg[u], tab + (n0 + u) * kAdjRow);
-                    const Quad<T> c4 = lds_quad(c6k, n0);
+                    Quad<T> c4{};
+                    if constexpr (kF32) c4 = lds_quad(c6k, n0);
+                    auto c6g = [&](int u) __attribute__((always_inline)) -> T {
+                        if constexpr (kF32) return c4.v[u];
+                        else return qg[u][6];
+                    };
                     auto level = [&](int u) __attribute__((always_inline)) {
                         const int n = n0 + u;
-                        const T on = __builtin_bit_cast(
-                            float, __builtin_amdgcn_readfirstlane(n >= kp ? 0x3f800000u : 0u));
-                        vset(n, rest(cL, n, qg[u], vget(n), incr(cL, qg[u], c4.v[u]), on, std::true_type{}));
-                        vset(n, rest(cT, n, qg[u], vget(n), incr(cT, qg[u], c4.v[u]), T(1), std::false_type{}));
+                        T on;
+                        if constexpr (kF32)
+                            on = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(n >= kp ? 0x3f800000u : 0u));
+                        else
+                            on = n >= kp ? 1.0 : 0.0;
+                        vset(n, rest(cL, n, qg[u], vget(n), incr(cL, qg[u], c6g(u)), on, std::true_type{}));
+                        vset(n, rest(cT, n, qg[u], vget(n), incr(cT, qg[u], c6g(u)), T(1), std::false_type{}));
                     };
                     level(3);
                     if (r <= 3) {
@@ -655,7 +659,7 @@ __device__ __forceinline__ void lmm_task(const LmmArgs &a, int m, int blk, int64
                             level(1);
                             if (r <= 1) {
                                 load_row(qg[0], tab + n0 * kAdjRow);
-                                vset(n0, rest(cT, n0, qg[0], vget(n0), incr(cT, qg[0], c4.v[0]), T(1),
+                                vset(n0, rest(cT, n0, qg[0], vget(n0), incr(cT, qg[0], c6g(0)), T(1),
                                               std::false_type{}));
                             }
                         }
