@@ -5,8 +5,10 @@
 
 namespace rq {
 
+// FP64: three waves per SIMD (167 VGPRs, no spills; left alone the compiler
+// keeps the FP64 polynomial constants in 227 and runs two waves: -4%)
 template <typename T, bool PERM, bool GRAD>
-__global__ __launch_bounds__(kBlock) void mbs_kernel(MbsArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 1))) void mbs_kernel(MbsArgs a)
 {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
